@@ -1,0 +1,239 @@
+"""Pins for the oracle's red-rec solve: replay validity, feasibility, exhaustive small grids,
+distance lower bounds and the hand-worked fixtures."""
+import glob
+import itertools
+import json
+import os
+import random
+from collections import deque
+
+import numpy as np
+import pytest
+from scipy.optimize import linear_sum_assignment
+
+import oracle
+from checker import check_solve, feasibility_margin
+from rr_inputs import pack_rows, bernoulli_grid, config_shots, shot_grid
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_from_tokens(w, h, tokens):
+    g = np.zeros((h, w), np.uint8)
+    for x, y in tokens:
+        g[y, x] = 1
+    return g
+
+
+def solve_dense(shape, dense, **kw):
+    return oracle.solve(shape, pack_rows(dense), **kw)
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.json"))))
+def test_golden_solve(path):
+    g = json.load(open(path))
+    shape = tuple(g["shape"])
+    dense = dense_from_tokens(shape[0], shape[1], g["tokens"])
+    r = solve_dense(shape, dense, trace=True)
+    assert r["rc"] == 0
+    assert r["status"] == g["status"]
+    assert [list(e) for e in r["events"]] == g["events"]
+    groups = []
+    goff = r["group_off"]
+    for k in range(len(goff) - 1):
+        groups.append([list(map(int, m)) for m in r["moves"][goff[k]:goff[k + 1]]])
+    assert groups == g["groups"]
+    assert r["n_steps"] == g["n_steps"]
+    fin = dense_from_tokens(shape[0], shape[1], g["final"])
+    assert np.array_equal(r["final"], pack_rows(fin))
+    check_solve(shape, pack_rows(dense), r)
+
+
+def random_shape(rng):
+    w = rng.choice([1, 2, 3, 5, 8, 13, 31, 64, 65, 70, 100, 130])
+    h = rng.choice([1, 2, 3, 5, 8, 13, 31, 64, 65, 70, 100, 130])
+    x0 = rng.randint(0, w - 1); x1 = rng.randint(x0 + 1, w)
+    y0 = rng.randint(0, h - 1); y1 = rng.randint(y0 + 1, h)
+    if rng.random() < 0.25:
+        x0, x1 = 0, w            # full-width band: the paper's own geometry
+    return (w, h, x0, y0, x1, y1)
+
+
+def test_random_instances_replay():
+    rng = random.Random(21)
+    n_ok = n_inf = 0
+    for i in range(600):
+        shape = random_shape(rng)
+        p = rng.choice([0.2, 0.4, 0.5, 0.6, 0.75, 0.9])
+        dense = bernoulli_grid(100, i, shape[0], shape[1], p)
+        r = solve_dense(shape, dense)
+        assert r["rc"] == 0
+        check_solve(shape, pack_rows(dense), r)
+        n_ok += r["status"] == 0
+        n_inf += r["status"] == 1
+    assert n_ok > 100 and n_inf > 50
+
+
+@pytest.mark.parametrize("name", ["single32", "single128", "batch64", "mixed"])
+def test_workload_instances_replay(name):
+    for d in config_shots(name, n=4):
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        occ = shot_grid(d)
+        r = oracle.solve(shape, occ)
+        check_solve(shape, occ, r)
+
+
+def all_rectangles(w, h):
+    for x0 in range(w):
+        for x1 in range(x0 + 1, w + 1):
+            for y0 in range(h):
+                for y1 in range(y0 + 1, h + 1):
+                    yield (w, h, x0, y0, x1, y1)
+
+
+def test_exhaustive_3x3_every_target():
+    """Every loading of a 3x3 grid against every target rectangle: valid replay, status given
+    by F, and a full-width band succeeds exactly when |S| >= |T| (§II.B)."""
+    w = h = 3
+    for bits in range(1 << 9):
+        dense = np.array([(bits >> i) & 1 for i in range(9)], np.uint8).reshape(h, w)
+        occ = pack_rows(dense)
+        for shape in all_rectangles(w, h):
+            r = oracle.solve(shape, occ)
+            check_solve(shape, occ, r)
+            if shape[2] == 0 and shape[4] == w:
+                t = (shape[4] - shape[2]) * (shape[5] - shape[3])
+                assert (r["status"] == 0) == (int(dense.sum()) >= t)
+
+
+def test_exhaustive_4x4_selected_targets():
+    w = h = 4
+    targets = [(4, 4, 1, 1, 3, 3), (4, 4, 0, 1, 4, 3), (4, 4, 1, 0, 3, 4), (4, 4, 0, 0, 2, 2),
+               (4, 4, 2, 3, 3, 4), (4, 4, 0, 0, 4, 4), (4, 4, 1, 1, 4, 2), (4, 4, 0, 2, 4, 4)]
+    for bits in range(1 << 16):
+        dense = np.array([(bits >> i) & 1 for i in range(16)], np.uint8).reshape(h, w)
+        occ = pack_rows(dense)
+        n = int(dense.sum())
+        for shape in targets:
+            r = oracle.solve(shape, occ)
+            if bits % 97 == 0:
+                check_solve(shape, occ, r)
+            else:
+                assert (r["status"] == 0) == (feasibility_margin(shape, dense) >= 0)
+            if r["status"] == 0:
+                assert n >= (shape[4] - shape[2]) * (shape[5] - shape[3])
+            if shape[2] == 0 and shape[4] == w:
+                assert (r["status"] == 0) == (n >= (shape[4] - shape[2]) * (shape[5] - shape[3]))
+
+
+def test_bfs_reachability_3x3():
+    """On a connected grid, unit token moves reach a cover of T iff |S| >= |T| (§II.B):
+    breadth-first search over all 2^9 configurations confirms the statement the feasibility
+    rule rests on, and that the oracle never claims fewer unit steps than the true minimum."""
+    w = h = 3
+    nbr = {}
+    for y in range(h):
+        for x in range(w):
+            nbr[y * w + x] = [yy * w + xx for xx, yy in ((x + 1, y), (x - 1, y), (x, y + 1), (x, y - 1))
+                              if 0 <= xx < w and 0 <= yy < h]
+    for shape in [(3, 3, 1, 1, 2, 2), (3, 3, 0, 1, 3, 2), (3, 3, 0, 0, 2, 2), (3, 3, 1, 0, 2, 3)]:
+        tmask = 0
+        for y in range(shape[3], shape[5]):
+            for x in range(shape[2], shape[4]):
+                tmask |= 1 << (y * w + x)
+        for start in range(1 << 9):
+            dist = {start: 0}
+            dq = deque([start])
+            found = None
+            while dq:
+                s = dq.popleft()
+                if s & tmask == tmask:
+                    found = dist[s]
+                    break
+                for c in range(9):
+                    if s >> c & 1:
+                        for nb in nbr[c]:
+                            if not s >> nb & 1:
+                                t = s & ~(1 << c) | (1 << nb)
+                                if t not in dist:
+                                    dist[t] = dist[s] + 1
+                                    dq.append(t)
+            n = bin(start).count("1")
+            assert (found is not None) == (n >= bin(tmask).count("1"))
+            dense = np.array([(start >> i) & 1 for i in range(9)], np.uint8).reshape(h, w)
+            r = oracle.solve(shape, pack_rows(dense))
+            if r["status"] == 0:
+                assert r["n_steps"] >= found
+
+
+def test_total_displacement_at_least_min_cost_matching():
+    """The minimum total displacement is a min-weight matching saturating T (§II.C); a valid
+    solution can never use fewer unit steps."""
+    rng = random.Random(31)
+    for i in range(200):
+        w, h = rng.randint(2, 12), rng.randint(2, 12)
+        shape = (w, h, *centre(w, h, rng))
+        dense = bernoulli_grid(200, i, w, h, rng.choice([0.5, 0.7]))
+        r = solve_dense(shape, dense)
+        if r["status"] != 0:
+            continue
+        src = np.argwhere(dense == 1)                           # (y, x)
+        tgt = [(y, x) for y in range(shape[3], shape[5]) for x in range(shape[2], shape[4])]
+        cost = np.array([[abs(sy - ty) + abs(sx - tx) for (sy, sx) in src] for (ty, tx) in tgt])
+        ri, ci = linear_sum_assignment(cost)
+        assert r["n_steps"] >= int(cost[ri, ci].sum())
+
+
+def centre(w, h, rng):
+    sw, sh = rng.randint(1, w), rng.randint(1, h)
+    x0, y0 = (w - sw) // 2, (h - sh) // 2
+    return (x0, y0, x0 + sw, y0 + sh)
+
+
+def test_full_width_with_balanced_columns_is_per_column_exact_1d():
+    """Full-width band and every column at zero surplus: red-rec reduces to exact 1D on each
+    column (Alg. 1, first loop); no row pre-pass and no redistribution happen."""
+    rng = random.Random(41)
+    for i in range(50):
+        w, h = rng.randint(1, 20), rng.randint(2, 20)
+        sh = rng.randint(1, h - 1)
+        y0 = rng.randint(0, h - sh)
+        dense = np.zeros((h, w), np.uint8)
+        for x in range(w):
+            for y in rng.sample(range(h), sh):
+                dense[y, x] = 1
+        shape = (w, h, 0, y0, w, y0 + sh)
+        r = solve_dense(shape, dense, trace=True)
+        assert r["status"] == 0 and r["events"] == []
+        expect = []
+        for x in range(w):
+            rows = [y for y in range(h) if dense[y, x]]
+            for s, d in oracle.e1d_moves(rows, y0, sh):
+                expect.append([x, s, x, d])
+        assert [list(map(int, m)) for m in r["moves"]] == expect
+
+
+def test_pair_loop_bounds():
+    """Each loop iteration settles at least one column, so there are at most W iterations
+    (§III.C complexity), and every event pairs a donor with a receiver."""
+    for d in config_shots("batch64", n=20) + config_shots("mixed", n=10):
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        r = oracle.solve(shape, shot_grid(d), trace=True)
+        if r["status"] != 0:
+            continue
+        assert len(r["events"]) <= d["w"]
+        for (i, j, kase, k, cnt) in r["events"]:
+            assert i != j and kase in (1, 2, 3) and cnt > 0
+
+
+def test_capacity_reporting():
+    d = config_shots("single32")[0]
+    shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+    occ = shot_grid(d)
+    full = oracle.solve(shape, occ)
+    small = oracle.solve(shape, occ, move_cap=5)
+    assert small["status"] == -2
+    assert small["need_moves"] == len(full["moves"])
+    assert small["need_groups"] == len(full["group_off"]) - 1
+    bad = oracle.solve((4, 4, 2, 2, 2, 3), np.zeros((4, 1), np.uint64))
+    assert bad["rc"] == -1
