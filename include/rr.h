@@ -1,0 +1,169 @@
+/*
+ * rr.h -- red-rec solver and batching routine for atom reconfiguration on MI355X (gfx950).
+ *
+ * Method: "Efficient algorithms to solve atom reconfiguration problems III: the bird and
+ * batching algorithms and other parallel implementations on GPUs" (arXiv 2504.06182):
+ * the redistribution-reconfiguration solver (§III.C, Alg. 1, run in the order of its parallel
+ * form, §III.D) on a rectangular trap grid, and the batching routine that merges its
+ * elementary displacements into simultaneous ones (§IV, Alg. 3, with its local constraint).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: W columns x H rows, 1 <= W, H <= 256 for the device kernels.  Column x runs left to
+ *    right, row y bottom to top (§III.C).  Target T = [x0,x1) x [y0,y1), non-empty, inside the
+ *    grid.
+ *  - Occupancy layout ("bit rows"): uint64_t[H][ws], ws = ceil(W/64); trap (x, y) is bit x%64 of
+ *    word y*ws + x/64.  Bits at x >= W are ignored on input and written as 0 on output.
+ *  - Unless stated otherwise every pointer argument is a DEVICE pointer owned by the caller; the
+ *    library never allocates, frees or synchronises inside these calls.  Work is enqueued on
+ *    `stream` (a hipStream_t; NULL = the default stream) and completes asynchronously.
+ *  - The return value reports only what the host can detect before launching: invalid
+ *    arguments (RR_E_INVAL), a grid beyond the supported size (RR_E_UNSUPPORTED), a workspace
+ *    smaller than the matching *_workspace_bytes() (RR_E_NOMEM) or a launch failure
+ *    (RR_E_DEVICE).  Outcomes that depend on the data are written to the device-side info
+ *    struct: RR_OK, RR_INFEASIBLE (no move, final = input), RR_E_CAPACITY (an output array is too
+ *    small; need_* hold the exact sizes, contents of the outputs are unspecified) or RR_E_INVAL
+ *    (malformed device-side input, e.g. a move off the grid).
+ *  - Every result is deterministic: the same input gives the same bytes, whatever the launch
+ *    configuration, and equals the CPU reference bit for bit.
+ *  - Calls on different streams that share no output or workspace memory may run concurrently.
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RR_OK = 0,
+    RR_INFEASIBLE = 1,
+    RR_E_INVAL = -1,
+    RR_E_CAPACITY = -2,
+    RR_E_DEVICE = -3,
+    RR_E_NOMEM = -4,
+    RR_E_INTERNAL = -5,
+    RR_E_UNSUPPORTED = -6
+} rr_status;
+
+/* Grid W x H and target rectangle [x0,x1) x [y0,y1). */
+typedef struct { uint16_t w, h, x0, y0, x1, y1; } rr_shape;
+
+/* One displacement (a path of the path system, §II.C): the token at (sx, sy) runs along row sy
+ * to column dx, then along column dx to (dx, dy).  Every emitted move has at least one step. */
+typedef struct { uint16_t sx, sy, dx, dy; } rr_move;
+
+/* Device-side result of a solve.  n_steps = summed path length (Manhattan) of all moves.
+ * need_moves / need_groups: exact sizes, filled in whenever the instance was solved or the
+ * capacity was short. */
+typedef struct {
+    int32_t status;
+    uint32_t n_moves, n_groups, n_steps, need_moves, need_groups;
+} rr_solve_info;
+
+/* Device-side result of a batching call. */
+typedef struct {
+    int32_t status;
+    uint32_t n_batches, n_steps, need_batches, need_steps;
+} rr_batch_info;
+
+/* Local constraints of the batching routine (§IV, "constrained batching"). */
+#define RR_LAMBDA_LINE_OR_COL 0u  /* same direction, and the moving tokens share a row or a column */
+#define RR_LAMBDA_ALONG       1u  /* same direction, on one line that runs along that direction */
+#define RR_LAMBDA_NONE        2u  /* only the vertex-disjointness of Alg. 3 */
+
+/* Largest grid side the device kernels take. */
+#define RR_MAX_SIDE 256u
+
+/* ------------------------------------------------------------------------------------------ */
+/* Single instance                                                                             */
+
+/* Bytes of device workspace rr_solve needs for this shape (0: none). */
+size_t rr_solve_workspace_bytes(rr_shape shape);
+
+/* Solve one instance with red-rec (§III.C-D, Alg. 1).
+ *   occ        [in]  bit rows of the initial loading (H*ws words).
+ *   moves      [out] rr_move[move_cap]; move_cap >= 2*(x1-x0)*(y1-y0) always suffices.
+ *   group_off  [out] uint32_t[group_cap + 1]: moves of group g are [group_off[g], group_off[g+1]);
+ *                    group_cap >= (x1-x0) + (y1-y0) always suffices.  Groups are, in order: one
+ *                    per target row with moves (row pre-pass), one per column of non-negative
+ *                    surplus with moves, one per receiver column in the order it was saturated.
+ *   final_occ  [out] bit rows of the grid after all moves (H*ws words).
+ *   info       [out] one rr_solve_info.
+ * Infeasible instances (too few tokens, §II.B) give status RR_INFEASIBLE, zero moves and
+ * final_occ = occ. */
+rr_status rr_solve(rr_shape shape, const uint64_t *occ,
+                   rr_move *moves, uint32_t move_cap,
+                   uint32_t *group_off, uint32_t group_cap,
+                   uint64_t *final_occ, rr_solve_info *info,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace rr_batch_moves needs for this shape and these capacities. */
+size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step_cap);
+
+/* Batch the moves of one solve (§IV, Alg. 3).
+ *   moves, group_off, sinfo [in]  the outputs of rr_solve (sinfo->n_moves / n_groups are read
+ *                                 on the device; a solve that did not end in RR_OK or
+ *                                 RR_INFEASIBLE makes the batch status RR_E_INVAL, and so does a
+ *                                 move off the grid, a move of length 0 or a malformed group_off).
+ *   move_cap   [in]  capacity of `moves` (>= sinfo->n_moves), used to size the workspace.
+ *   flags      [in]  RR_LAMBDA_*.
+ *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).
+ *   steps      [out] uint32_t[step_cap]: dir << 30 | x << 15 | y, the source trap of each unit
+ *                    step, dir 0 = +x, 1 = -x, 2 = +y, 3 = -y.  step_cap >= sinfo->n_steps and
+ *                    batch_cap >= sinfo->n_steps always suffice.
+ *   binfo      [out] one rr_batch_info.  When the summed path length exceeds step_cap the status
+ *                    is RR_E_CAPACITY with need_steps exact and need_batches = need_steps (an
+ *                    upper bound); when only batch_cap is short, both need_* are exact.
+ *   workspace  [in]  device scratch of rr_batch_workspace_bytes(shape, move_cap, step_cap) bytes,
+ *                    owned by the caller, not shared with a concurrent call. */
+rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const uint32_t *group_off,
+                         const rr_solve_info *sinfo, uint32_t move_cap, uint32_t flags,
+                         uint32_t *batch_off, uint32_t batch_cap,
+                         uint32_t *steps, uint32_t step_cap, rr_batch_info *binfo,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
+/* Many independent instances in one launch                                                   */
+
+/* Per-instance descriptor of a many-instance launch (device memory, one per instance, 80
+ * bytes, no implicit padding).  Offsets are element counts into the arenas passed to the call:
+ *   occ_off    uint64 words: the instance's input bit rows and its final bit rows (same offset
+ *              in the input arena and in the final arena)
+ *   move_off   rr_move elements (move_cap of them)
+ *   group_off  uint32 elements (group_cap + 1 of them)
+ *   step_off   uint32 elements (step_cap of them)           -- rr_batch_moves_many only
+ *   batch_off  uint32 elements (batch_cap + 1 of them)      -- rr_batch_moves_many only
+ *   ws_off     bytes into the batching workspace, at least
+ *              rr_batch_workspace_bytes(shape, move_cap, step_cap) apart -- rr_batch_moves_many */
+typedef struct {
+    rr_shape shape;
+    uint16_t pad0, pad1;
+    uint32_t move_cap, group_cap, step_cap, batch_cap;
+    uint64_t occ_off, move_off, group_off, step_off, batch_off, ws_off;
+} rr_desc;
+
+/* Solve n instances in one launch; instance i reads occ_arena + desc[i].occ_off and writes
+ * moves/group offsets/final bit rows at its offsets and infos[i].  Results are bit-identical to
+ * n calls of rr_solve.  max_w / max_h bound every instance's grid (they pick the kernel
+ * variant; an instance beyond them gets RR_E_INVAL). */
+rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
+                        const uint64_t *occ_arena, rr_move *move_arena, uint32_t *group_arena,
+                        uint64_t *final_arena, rr_solve_info *infos, void *stream);
+
+/* Batch the moves of n solved instances in one launch (same semantics as rr_batch_moves). */
+rr_status rr_batch_moves_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
+                              const rr_move *move_arena, const uint32_t *group_arena,
+                              const rr_solve_info *sinfos, uint32_t flags,
+                              uint32_t *batch_arena, uint32_t *step_arena, rr_batch_info *binfos,
+                              void *workspace, size_t workspace_bytes, void *stream);
+
+/* Library version string (host). */
+const char *rr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RR_H */

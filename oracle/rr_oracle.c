@@ -490,8 +490,7 @@ static int solve_impl(const o_shape *shape, const uint64_t *occ, o_move *moves, 
         info->status = S.status;
         info->need_moves = 0; info->need_groups = 0;
         if (group_off) group_off[0] = 0;
-        if (final_occ) memcpy(final_occ, occ, sizeof(uint64_t) * (size_t)H * ws);
-        goto done;
+        goto write_final;                  /* no move was made: the final grid is the input */
     }
     uint64_t steps = 0;
     for (size_t b = 0; b < S.L.n; ++b)
@@ -508,6 +507,7 @@ static int solve_impl(const o_shape *shape, const uint64_t *occ, o_move *moves, 
     info->n_moves = (uint32_t)S.L.n;
     info->n_groups = (uint32_t)S.L.ng;
     info->n_steps = (uint32_t)steps;
+write_final:
     if (final_occ) {
         memset(final_occ, 0, sizeof(uint64_t) * (size_t)H * ws);
         for (int y = 0; y < H; ++y)
@@ -636,6 +636,15 @@ int rr_oracle_batch_moves(const o_shape *shape, const o_move *mv, const uint32_t
         if (mv[b].sx >= W || mv[b].dx >= W || mv[b].sy >= H || mv[b].dy >= H || path_len(&mv[b]) == 0) {
             bi->status = O_E_INVAL; return O_OK;
         }
+
+    /* steps capacity first: without room for every step nothing is batched; need_batches is
+     * then reported as the step count, an upper bound on the number of batches */
+    uint64_t T = 0;
+    for (uint32_t b = 0; b < K; ++b) T += (uint64_t)path_len(&mv[b]);
+    if (T > step_cap) {
+        bi->status = O_E_CAPACITY; bi->need_steps = (uint32_t)T; bi->need_batches = (uint32_t)T;
+        return O_OK;
+    }
 
     int rc = O_OK;
     size_t WH = (size_t)W * H, gw = (WH + 63) / 64;

@@ -1,0 +1,697 @@
+// rr_solve.hip -- red-rec solve on gfx950: one 256-thread workgroup (4 wave64) per instance.
+//
+// Method (arXiv 2504.06182): exact 1D on lines (§III.A), red-rec with every column of
+// non-negative surplus solved from the outset and donor/receiver pairs identified one after the
+// other (§III.C, Alg. 1; ordering of §III.D).  Targets narrower than the grid get a row
+// pre-pass first (each target row solved on its own line), and the column stage then treats
+// side columns as donors with no target.
+//
+// Data flow inside one workgroup, all in LDS:
+//   bit rows (coalesced load)  -> row pre-pass, one wave per target row
+//   -> column bits by ballot transposition (one ballot per column and 64-row slab)
+//   -> column counts and surplus by popcount
+//   -> non-negative columns: exact 1D by prefix sums of d_k = q_k - k, one wave per column
+//   -> donor/receiver loop on wave 0 (ballot masks of unsettled columns, 64-bit pair keys,
+//      receiver split cost in closed form from prefix sums)
+//   -> receiver solves, whole workgroup, ranks by counting
+//   -> every output position from a workgroup exclusive scan (no atomics decide an order)
+//   -> final grid by ballot transposition back to bit rows.
+#include "rr_device.hpp"
+#include "rr.h"
+
+namespace rr {
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / kWave;
+
+enum { M_STEPS = 0, M_NEV = 1, M_ERR = 2 };
+
+template <int S>
+struct SolveLds {
+    static constexpr int WS = S / 64;
+    uint64_t rows[S * WS];   // bit rows, stride ws
+    uint64_t cols[S * WS];   // column bits after the row pre-pass, stride hs
+    uint64_t elig[S * WS];   // column bits that count towards the column surplus, stride hs
+    int rowW[S], rowT0[S], rowN[S], rowR[S], rowCnt[S], rowOff[S];
+    int colA[S], colW[S], colU[S], colCnt[S], colOff[S], sp[S], sig[S], bcnt[S], ubeg[S];
+    int mNb[S], mSb[S], mNt[S], mSt[S];
+    int16_t evI[S + 1], evJ[S + 1], evK[S + 1], evC[S + 1], evBlo[S + 1], evBhi[S + 1], evUlo[S + 1], evUhi[S + 1];
+    int P[kWaves][S + 1];
+    int Q[kWaves][S + 2];
+    uint64_t rkey[S];
+    int16_t ry[S], rorg[S], byRank[S];
+    int scanA[kWaves];
+    int scanB[kWaves];
+    int misc[8];
+};
+
+struct SolveArgs {
+    int W, H, x0, y0, x1, y1;
+    const uint64_t *occ;
+    rr_move *moves;
+    uint32_t move_cap;
+    uint32_t *goff;
+    uint32_t group_cap;
+    uint64_t *fin;
+    rr_solve_info *info;
+};
+
+// ------------------------------------------------------------------------------------------
+// workgroup helpers
+
+__device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
+{
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == kWave - 1) tmp[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        int t = tmp[w];
+        off += (w < wid) ? t : 0;
+        tot += t;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__device__ __forceinline__ int block_sum(int v, int *tmp)
+{
+    int tot;
+    block_excl_scan(v, tmp, &tot);
+    return tot;
+}
+
+// positions of the set bits of bits[0..nw) (word j = positions 64j..64j+63) -> P, in order
+__device__ __forceinline__ int compact_bits_wave(const uint64_t *bits, int nw, int *P)
+{
+    const int lane = lane_id();
+    int base = 0;
+    for (int j = 0; j < nw; ++j) {
+        uint64_t w = bits[j];
+        if ((w >> lane) & 1ull) P[base + popc(w & low_mask(lane))] = 64 * j + lane;
+        base += popc(w);
+    }
+    wave_sync();
+    return base;
+}
+
+// Qs[m] = sum_{k<m} V[k], m = 0..n
+__device__ __forceinline__ void prefix_sums_wave(const int *V, int n, int *Qs)
+{
+    const int lane = lane_id();
+    int carry = 0;
+    for (int base = 0; base < n; base += kWave) {
+        int k = base + lane;
+        int v = k < n ? V[k] : 0;
+        int inc = wave_incl_scan(v);
+        if (k < n) Qs[k + 1] = carry + inc;
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) Qs[0] = 0;
+    wave_sync();
+}
+
+// Exact-1D assignment on a line (§III.A): sorted sources P[0..a), targets b..b+t-1, a >= t.
+// The optimum is an order-preserving match of a run of t consecutive sources starting at w;
+// cost(w) = sum_{k in [w,w+t)} |d_k - (b - w)| with d_k = P[k] - k non-decreasing, evaluated in
+// O(log a) from prefix sums of d and a binary search for the sign change.  Lanes take
+// windows; the minimum cost wins, on equal cost the smallest w.
+__device__ int e1d_window_wave(const int *P, int *Qs, int a, int b, int t)
+{
+    const int lane = lane_id();
+    if (t >= a) return 0;
+    int carry = 0;
+    for (int base = 0; base < a; base += kWave) {
+        int k = base + lane;
+        int d = k < a ? P[k] - k : 0;
+        int inc = wave_incl_scan(d);
+        if (k < a) Qs[k + 1] = carry + inc;
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) Qs[0] = 0;
+    wave_sync();
+    uint64_t best = ~0ull;
+    for (int w = lane; w + t <= a; w += kWave) {
+        const int c = b - w;
+        int lo = w, hi = w + t;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (P[mid] - mid < c) lo = mid + 1; else hi = mid;
+        }
+        const int s = lo;
+        long cost = (long)c * (s - w) - (long)(Qs[s] - Qs[w]) + (long)(Qs[w + t] - Qs[s]) - (long)c * (w + t - s);
+        uint64_t key = ((uint64_t)cost << 20) | (uint64_t)w;
+        best = key < best ? key : best;
+    }
+    best = wave_min_u64(best);
+    wave_sync();
+    return (int)(best & 0xFFFFFull);
+}
+
+// k-th set bit (0-based) of a multi-word bitset
+__device__ __forceinline__ int select_in_bits(const uint64_t *bits, int nw, int k)
+{
+    for (int j = 0; j < nw; ++j) {
+        int c = popc(bits[j]);
+        if (k < c) return 64 * j + select_bit(bits[j], k);
+        k -= c;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ void put_move(const SolveArgs &A, uint32_t pos, int sx, int sy, int dx, int dy)
+{
+    if (pos < A.move_cap) {
+        uint64_t v = (uint64_t)(uint16_t)sx | ((uint64_t)(uint16_t)sy << 16) |
+                     ((uint64_t)(uint16_t)dx << 32) | ((uint64_t)(uint16_t)dy << 48);
+        reinterpret_cast<uint64_t *>(A.moves)[pos] = v;
+    }
+}
+
+// Emit the moves of one exact-1D line: matched pairs P[w0+k] -> t0+k, k < n.  Paths towards
+// larger coordinates first, largest target first; then paths towards smaller coordinates,
+// smallest target first (§III.A, generating moves).  Positions by ballot prefix counts.
+__device__ __forceinline__ void emit_line_wave(const SolveArgs &A, const int *P, int w0, int t0, int n, int R,
+                                               uint32_t off, bool horizontal, int fixed)
+{
+    const int lane = lane_id();
+    int rb = 0, lb = 0;
+    for (int base = 0; base < n; base += kWave) {
+        const int k = base + lane;
+        int s = 0, t = 0;
+        bool isR = false, isL = false;
+        if (k < n) { s = P[w0 + k]; t = t0 + k; isR = s < t; isL = s > t; }
+        const uint64_t mR = ballot(isR), mL = ballot(isL);
+        int pos = -1;
+        if (isR) pos = R - (rb + popc(mR & low_mask(lane + 1)));
+        else if (isL) pos = R + lb + popc(mL & low_mask(lane));
+        if (pos >= 0) {
+            if (horizontal) put_move(A, off + pos, s, fixed, t, fixed);
+            else put_move(A, off + pos, fixed, s, fixed, t);
+        }
+        rb += popc(mR);
+        lb += popc(mL);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// donor/receiver loop (Alg. 1 main loop, pairing rule of §III.C), run by wave 0
+
+template <int S>
+__device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
+{
+    const int lane = lane_id();
+    constexpr int CW = S / 64;
+    int nev = 0, err = 0;
+    for (int iter = 0; iter <= W; ++iter) {
+        uint64_t nz[CW];
+        bool anyneg = false;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int x = 64 * c + lane;
+            const int v = x < W ? L.sp[x] : 0;
+            nz[c] = ballot(v != 0);
+            anyneg |= ballot(v < 0) != 0ull;
+        }
+        if (!anyneg) break;
+        if (iter == W) { err = 1; break; }
+        // candidate pairs: adjacent unsettled columns of opposite sign
+        uint64_t best = 0;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int x = 64 * c + lane;
+            if (!((nz[c] >> lane) & 1ull)) continue;
+            int nx = -1;
+            const uint64_t rest = nz[c] & ~low_mask(lane + 1);
+            if (rest) nx = 64 * c + __ffsll((unsigned long long)rest) - 1;
+            else {
+#pragma unroll
+                for (int c2 = c + 1; c2 < CW; ++c2)
+                    if (nx < 0 && nz[c2]) nx = 64 * c2 + __ffsll((unsigned long long)nz[c2]) - 1;
+            }
+            if (nx < 0) continue;
+            const int vx = L.sp[x], vn = L.sp[nx];
+            if ((vx > 0) == (vn > 0)) continue;
+            const int i = vx > 0 ? x : nx, j = vx > 0 ? nx : x;
+            const int si = vx > 0 ? vx : vn, need = vx > 0 ? -vn : -vx;
+            const int m = si < need ? si : need;
+            const int dist = i > j ? i - j : j - i;
+            // larger exchange, then fewer columns between, then receiver closer to saturation,
+            // then smaller receiver index, then smaller donor index
+            const uint64_t key = ((uint64_t)m << 50) | ((uint64_t)(4095 - dist) << 38) |
+                                 ((uint64_t)(8191 - need) << 25) | ((uint64_t)(4095 - j) << 13) |
+                                 (uint64_t)(8191 - i);
+            best = key > best ? key : best;
+        }
+        best = wave_max_u64(best);
+        if (best == 0) { err = 1; break; }
+        const int j = 4095 - (int)((best >> 13) & 4095ull);
+        const int i = 8191 - (int)(best & 8191ull);
+        const int si = L.sp[i], d = -L.sp[j];
+        const int ai = L.colA[i], bc = L.bcnt[i], ub = L.ubeg[i];
+        int *P0 = L.P[0];
+        int *Q0 = L.Q[0];
+        compact_bits_wave(&L.elig[i * hs], hs, P0);
+        prefix_sums_wave(P0, ai, Q0);
+        if (si < d) {
+            // case 3: the donor's whole pool is marked for the receiver
+            if (lane == 0) {
+                L.mNb[j] += bc;
+                L.mSb[j] += Q0[bc];
+                L.mNt[j] += ai - ub;
+                L.mSt[j] += Q0[ai] - Q0[ub];
+                L.evI[nev] = (int16_t)i; L.evJ[nev] = (int16_t)j; L.evC[nev] = 3; L.evK[nev] = -1;
+                L.evBlo[nev] = 0; L.evBhi[nev] = (int16_t)bc; L.evUlo[nev] = (int16_t)ub; L.evUhi[nev] = (int16_t)ai;
+                L.bcnt[i] = 0; L.ubeg[i] = ai;
+                L.sp[j] = si - d; L.sp[i] = 0;
+            }
+        } else {
+            // cases 1-2: d tokens, the k nearest below the band and the d-k nearest above it,
+            // k minimising the receiver's 1-D cost (ties: largest k)
+            int *P1 = L.P[1], *Q1 = L.Q[1], *E = L.P[2], *EQ = L.Q[2];
+            const int aj = L.colA[j];
+            compact_bits_wave(&L.elig[j * hs], hs, P1);
+            prefix_sums_wave(P1, aj, Q1);
+            int nbO = 0, ntO = 0;
+            for (int sl = 0; sl < hs; ++sl) {
+                const uint64_t e = L.elig[j * hs + sl];
+                nbO += popc(e & low_mask(y0 - 64 * sl));
+                ntO += popc(e & ~low_mask(y1 - 64 * sl));
+            }
+            const int nband = aj - nbO - ntO;
+            const int sbO = Q1[nbO], stO = Q1[aj] - Q1[aj - ntO];
+            for (int m = lane; m < nband; m += kWave) E[m] = P1[nbO + m] - y0 - m;
+            wave_sync();
+            prefix_sums_wave(E, nband, EQ);
+            const int nbF = nbO + L.mNb[j], sbF = sbO + L.mSb[j], ntF = ntO + L.mNt[j], stF = stO + L.mSt[j];
+            const int uav = ai - ub;
+            const int klo = d - uav > 0 ? d - uav : 0, khi = d < bc ? d : bc;
+            uint64_t bk = ~0ull;
+            for (int k = klo + lane; k <= khi; k += kWave) {
+                const long nb = nbF + k, nt = ntF + d - k;
+                const long Sb = sbF + (Q0[bc] - Q0[bc - k]);
+                const long St = stF + (Q0[ub + d - k] - Q0[ub]);
+                const long cb = nb * y0 + nb * (nb - 1) / 2 - Sb;
+                const long ct = St - nt * y0 - nt * (2L * sh - nt - 1) / 2;
+                int lo = 0, hi = nband;
+                while (lo < hi) {
+                    int mid = (lo + hi) >> 1;
+                    if (E[mid] < nb) lo = mid + 1; else hi = mid;
+                }
+                const long cband = nb * lo - EQ[lo] + (EQ[nband] - EQ[lo]) - nb * (nband - lo);
+                const long cost = cb + cband + ct;
+                const uint64_t key = ((uint64_t)cost << 16) | (uint64_t)(0xFFFF - k);
+                bk = key < bk ? key : bk;
+            }
+            bk = wave_min_u64(bk);
+            const int k = 0xFFFF - (int)(bk & 0xFFFFull);
+            if (lane == 0) {
+                L.evI[nev] = (int16_t)i; L.evJ[nev] = (int16_t)j; L.evC[nev] = (int16_t)(si == d ? 2 : 1);
+                L.evK[nev] = (int16_t)k;
+                L.evBlo[nev] = (int16_t)(bc - k); L.evBhi[nev] = (int16_t)bc;
+                L.evUlo[nev] = (int16_t)ub; L.evUhi[nev] = (int16_t)(ub + d - k);
+                L.bcnt[i] = bc - k; L.ubeg[i] = ub + d - k;
+                L.sp[i] = si - d; L.sp[j] = 0;
+            }
+        }
+        ++nev;
+        wave_sync();
+    }
+    if (lane == 0) { L.misc[M_NEV] = nev; L.misc[M_ERR] |= err; }
+}
+
+// ------------------------------------------------------------------------------------------
+
+template <int S>
+__device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    const int W = A.W, H = A.H, x0 = A.x0, y0 = A.y0, x1 = A.x1, y1 = A.y1;
+    const int sw = x1 - x0, sh = y1 - y0;
+    const int ws = (W + 63) >> 6, hs = (H + 63) >> 6;
+    const bool side = (x0 > 0 || x1 < W);
+    int *P = L.P[wid];
+    int *Q = L.Q[wid];
+
+    // bit rows in, padding dropped
+    for (int i = tid; i < H * ws; i += kThreads) {
+        const int j = i % ws;
+        L.rows[i] = A.occ[i] & low_mask(W - 64 * j);
+    }
+    if (tid < 8) L.misc[tid] = 0;
+    __syncthreads();
+
+    // feasibility: F = N - D - sw*sh, D = band-row tokens beyond sw (parked in side columns)
+    int myN = 0, myD = 0;
+    if (tid < H) {
+        int a = 0;
+        for (int j = 0; j < ws; ++j) a += popc(L.rows[tid * ws + j]);
+        myN = a;
+        if (side && tid >= y0 && tid < y1) myD = a > sw ? a - sw : 0;
+    }
+    const int N = block_sum(myN, L.scanA);
+    const int D = block_sum(myD, L.scanB);
+    if ((long)N - D - (long)sw * sh < 0) {
+        for (int i = tid; i < H * ws; i += kThreads) A.fin[i] = L.rows[i];
+        if (tid == 0) {
+            A.goff[0] = 0;
+            rr_solve_info inf = {RR_INFEASIBLE, 0u, 0u, 0u, 0u, 0u};
+            *A.info = inf;
+        }
+        return;
+    }
+
+    // ---- row pre-pass: each target row solved on its own line -----------------------------
+    int nH = 0, gH = 0;
+    if (side) {
+        for (int y = y0 + wid; y < y1; y += kWaves) {
+            const int a = compact_bits_wave(&L.rows[y * ws], ws, P);
+            int w0, t0, n;
+            if (a >= sw) { w0 = e1d_window_wave(P, Q, a, x0, sw); t0 = x0; n = sw; }
+            else { w0 = 0; t0 = x0 + (sw - a) / 2; n = a; }
+            int r = 0, c = 0, st = 0;
+            for (int k = lane; k < n; k += kWave) {
+                const int s = P[w0 + k], t = t0 + k;
+                r += s < t; c += s != t; st += s < t ? t - s : s - t;
+            }
+            r = wave_sum(r); c = wave_sum(c); st = wave_sum(st);
+            if (lane == 0) {
+                L.rowW[y] = w0; L.rowT0[y] = t0; L.rowN[y] = n; L.rowR[y] = r; L.rowCnt[y] = c;
+                atomicAdd(&L.misc[M_STEPS], st);
+            }
+            wave_sync();
+        }
+        __syncthreads();
+        const int cnt = tid < sh ? L.rowCnt[y0 + tid] : 0;
+        const int off = block_excl_scan(cnt, L.scanA, &nH);
+        const int gi = block_excl_scan(cnt > 0 ? 1 : 0, L.scanB, &gH);
+        if (tid < sh) {
+            L.rowOff[y0 + tid] = off;
+            if (cnt > 0 && gi <= (int)A.group_cap) A.goff[gi] = (uint32_t)off;
+        }
+        __syncthreads();
+        for (int y = y0 + wid; y < y1; y += kWaves) {
+            const int a = compact_bits_wave(&L.rows[y * ws], ws, P);
+            const int w0 = L.rowW[y], t0 = L.rowT0[y], n = L.rowN[y];
+            if (L.rowCnt[y] > 0) emit_line_wave(A, P, w0, t0, n, L.rowR[y], (uint32_t)L.rowOff[y], true, y);
+            if (lane < ws) {
+                const uint64_t old = L.rows[y * ws + lane];
+                const int sh64 = 64 * lane;
+                uint64_t nw;
+                if (a >= sw) {
+                    const int lo = P[w0], hi = P[w0 + sw - 1];
+                    nw = (old & ~range_mask(lo - sh64, hi - sh64)) | range_mask(x0 - sh64, x1 - 1 - sh64);
+                } else {
+                    nw = range_mask(t0 - sh64, t0 + a - 1 - sh64);
+                }
+                L.rows[y * ws + lane] = nw;
+            }
+            wave_sync();
+        }
+        __syncthreads();
+    }
+
+    // ---- column bits by ballot transposition ----------------------------------------------
+    for (int p = wid; p < W * hs; p += kWaves) {
+        const int x = p / hs, sl = p - x * hs;
+        const int y = 64 * sl + lane;
+        const bool bit = (y < H) && ((L.rows[y * ws + (x >> 6)] >> (x & 63)) & 1ull);
+        const uint64_t m = ballot(bit);
+        if (lane == 0) L.cols[x * hs + sl] = m;
+    }
+    __syncthreads();
+
+    // ---- surplus per column (Alg. 1): central columns count every token, side columns only
+    //      their reservoir rows
+    if (tid < W) {
+        const int x = tid;
+        const bool central = (x >= x0 && x < x1);
+        int a = 0, nbelow = 0;
+        for (int sl = 0; sl < hs; ++sl) {
+            const uint64_t c = L.cols[x * hs + sl];
+            const uint64_t band = range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
+            const uint64_t e = central ? c : (c & ~band);
+            L.elig[x * hs + sl] = e;
+            a += popc(e);
+            nbelow += popc(e & low_mask(y0 - 64 * sl));
+        }
+        const int sigma = a - (central ? sh : 0);
+        L.colA[x] = a; L.sig[x] = sigma; L.sp[x] = sigma; L.colCnt[x] = 0;
+        L.bcnt[x] = nbelow; L.ubeg[x] = nbelow;
+        L.mNb[x] = 0; L.mSb[x] = 0; L.mNt[x] = 0; L.mSt[x] = 0;
+    }
+    __syncthreads();
+
+    // ---- columns of non-negative surplus, solved from the outset (§III.D) -----------------
+    for (int x = x0 + wid; x < x1; x += kWaves) {
+        if (L.sig[x] < 0) continue;
+        const int a = compact_bits_wave(&L.elig[x * hs], hs, P);
+        const int w0 = e1d_window_wave(P, Q, a, y0, sh);
+        int u = 0, c = 0, st = 0;
+        for (int k = lane; k < sh; k += kWave) {
+            const int s = P[w0 + k], t = y0 + k;
+            u += s < t; c += s != t; st += s < t ? t - s : s - t;
+        }
+        u = wave_sum(u); c = wave_sum(c); st = wave_sum(st);
+        if (lane == 0) {
+            L.colW[x] = w0; L.colU[x] = u; L.colCnt[x] = c;
+            L.bcnt[x] = w0; L.ubeg[x] = w0 + sh;
+            atomicAdd(&L.misc[M_STEPS], st);
+        }
+        wave_sync();
+    }
+    __syncthreads();
+    int nA, gA;
+    {
+        const int cnt = tid < W ? L.colCnt[tid] : 0;
+        const int off = block_excl_scan(cnt, L.scanA, &nA);
+        const int gi = block_excl_scan(cnt > 0 ? 1 : 0, L.scanB, &gA);
+        if (tid < W) {
+            L.colOff[tid] = nH + off;
+            if (cnt > 0 && gH + gi <= (int)A.group_cap) A.goff[gH + gi] = (uint32_t)(nH + off);
+        }
+    }
+    __syncthreads();
+    for (int x = x0 + wid; x < x1; x += kWaves) {
+        if (L.sig[x] < 0 || L.colCnt[x] == 0) continue;
+        compact_bits_wave(&L.elig[x * hs], hs, P);
+        emit_line_wave(A, P, L.colW[x], y0, sh, L.colU[x], (uint32_t)L.colOff[x], false, x);
+        wave_sync();
+    }
+    __syncthreads();
+
+    // ---- donor/receiver pairs ---------------------------------------------------------------
+    if (wid == 0) pair_loop<S>(L, W, hs, y0, y1, sh);
+    __syncthreads();
+    const int nev = L.misc[M_NEV];
+
+    // ---- receiver solves, in the order receivers were saturated ------------------------------
+    int off = nH + nA, g = gH + gA;
+    for (int e = 0; e < nev; ++e) {
+        if (L.evC[e] == 3) continue;
+        const int j = L.evJ[e];
+        const int aj = L.colA[j];
+        if (tid < aj && tid < S) { L.ry[tid] = (int16_t)select_in_bits(&L.elig[j * hs], hs, tid); L.rorg[tid] = (int16_t)j; }
+        int base = aj;
+        for (int e2 = 0; e2 <= e; ++e2) {
+            if (L.evJ[e2] != j) continue;
+            const int i = L.evI[e2];
+            const int blo = L.evBlo[e2], nb = L.evBhi[e2] - blo;
+            const int ulo = L.evUlo[e2], nu = L.evUhi[e2] - ulo;
+            if (tid < nb + nu && base + tid < S) {
+                const int idx = tid < nb ? blo + tid : ulo + (tid - nb);
+                L.ry[base + tid] = (int16_t)select_in_bits(&L.elig[i * hs], hs, idx);
+                L.rorg[base + tid] = (int16_t)i;
+            }
+            base += nb + nu;
+        }
+        if (base != sh) { if (tid == 0) L.misc[M_ERR] = 1; break; }
+        __syncthreads();
+        // order of sources: by row; tokens standing in one row reach column j in order of
+        // distance (own first, then nearer donor, then left donor) and the first to arrive
+        // takes the target farther from that row
+        if (tid < sh) {
+            const int y = L.ry[tid], o = L.rorg[tid];
+            const long h = (long)(o > j ? o - j : j - o) * W + o;
+            const long tau = (y >= y1) ? h : (y < y0 ? -h : 0);
+            L.rkey[tid] = ((uint64_t)y << 32) + (uint64_t)(tau + (1L << 30));
+        }
+        __syncthreads();
+        int up = 0, dn = 0;
+        if (tid < sh) {
+            const uint64_t k = L.rkey[tid];
+            int r = 0;
+            for (int s = 0; s < sh; ++s) r += L.rkey[s] < k;
+            L.byRank[r] = (int16_t)tid;
+        }
+        __syncthreads();
+        int y = 0, o = 0, t = 0;
+        if (tid < sh) {
+            const int src = L.byRank[tid];
+            y = L.ry[src]; o = L.rorg[src]; t = y0 + tid;
+            const bool moving = (o != j) || (y != t);
+            up = moving && t >= y;
+            dn = moving && t < y;
+        }
+        int nUp, nDn;
+        const int upEx = block_excl_scan(up, L.scanA, &nUp);
+        const int dnEx = block_excl_scan(dn, L.scanB, &nDn);
+        if (up) put_move(A, (uint32_t)(off + nUp - (upEx + 1)), o, y, j, t);
+        if (dn) put_move(A, (uint32_t)(off + nUp + dnEx), o, y, j, t);
+        int st = (up || dn) ? ((o > j ? o - j : j - o) + (t > y ? t - y : y - t)) : 0;
+        st = wave_sum(st);
+        if (lane == 0 && st) atomicAdd(&L.misc[M_STEPS], st);
+        if (nUp + nDn > 0) {
+            if (tid == 0 && g <= (int)A.group_cap) A.goff[g] = (uint32_t)off;
+            ++g;
+            off += nUp + nDn;
+        }
+        __syncthreads();
+    }
+
+    // ---- final grid: band full in central columns, parked tokens, remaining pools -----------
+    if (tid < W) {
+        const int x = tid;
+        const bool central = (x >= x0 && x < x1);
+        const bool donor = !central || L.sig[x] >= 0;
+        int keepLow = L.bcnt[x], dropLow = L.ubeg[x];   // pool left: indices [0,bcnt) and [ubeg,a)
+        for (int sl = 0; sl < hs; ++sl) {
+            const uint64_t band = range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
+            uint64_t f = central ? band : (L.cols[x * hs + sl] & band);
+            if (donor) {
+                const uint64_t e = L.elig[x * hs + sl];
+                const int c = popc(e);
+                uint64_t lowPart;
+                if (keepLow >= c) lowPart = e;
+                else lowPart = keepLow > 0 ? (e & low_mask(select_bit(e, keepLow))) : 0ull;
+                uint64_t dropPart;
+                if (dropLow >= c) dropPart = e;
+                else dropPart = dropLow > 0 ? (e & low_mask(select_bit(e, dropLow))) : 0ull;
+                f |= lowPart | (e & ~dropPart);
+                keepLow = keepLow > c ? keepLow - c : 0;
+                dropLow = dropLow > c ? dropLow - c : 0;
+            }
+            L.cols[x * hs + sl] = f;
+        }
+    }
+    __syncthreads();
+    for (int p = wid; p < H * ws; p += kWaves) {
+        const int y = p / ws, j = p - y * ws;
+        const int x = 64 * j + lane;
+        const bool bit = (x < W) && ((L.cols[x * hs + (y >> 6)] >> (y & 63)) & 1ull);
+        const uint64_t m = ballot(bit);
+        if (lane == 0) A.fin[p] = m;
+    }
+
+    if (tid == 0) {
+        const uint32_t nm = (uint32_t)off, ng = (uint32_t)g;
+        if (ng <= A.group_cap) A.goff[ng] = nm;
+        rr_solve_info inf;
+        const bool err = L.misc[M_ERR] != 0;
+        const bool cap = nm > A.move_cap || ng > A.group_cap;
+        inf.status = err ? RR_E_INTERNAL : (cap ? RR_E_CAPACITY : RR_OK);
+        const bool ok = inf.status == RR_OK;
+        inf.n_moves = ok ? nm : 0u;
+        inf.n_groups = ok ? ng : 0u;
+        inf.n_steps = ok ? (uint32_t)L.misc[M_STEPS] : 0u;
+        inf.need_moves = nm;
+        inf.need_groups = ng;
+        *A.info = inf;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_solve_one(SolveArgs A)
+{
+    __shared__ SolveLds<S> L;
+    solve_one<S>(L, A);
+}
+
+template <int S>
+__global__ __launch_bounds__(kThreads) void k_solve_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
+                                                         const uint64_t *occ, rr_move *mv, uint32_t *ga,
+                                                         uint64_t *fa, rr_solve_info *infos)
+{
+    __shared__ SolveLds<S> L;
+    const rr_desc d = desc[blockIdx.x];
+    const rr_shape s = d.shape;
+    const bool ok = s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= S && s.h <= S &&
+                    s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
+    if (!ok) {
+        if (threadIdx.x == 0) {
+            rr_solve_info inf = {RR_E_INVAL, 0u, 0u, 0u, 0u, 0u};
+            infos[blockIdx.x] = inf;
+        }
+        return;
+    }
+    SolveArgs A;
+    A.W = s.w; A.H = s.h; A.x0 = s.x0; A.y0 = s.y0; A.x1 = s.x1; A.y1 = s.y1;
+    A.occ = occ + d.occ_off;
+    A.moves = mv + d.move_off;
+    A.move_cap = d.move_cap;
+    A.goff = ga + d.group_off;
+    A.group_cap = d.group_cap;
+    A.fin = fa + d.occ_off;
+    A.info = infos + blockIdx.x;
+    solve_one<S>(L, A);
+}
+
+}  // namespace rr
+
+using namespace rr;
+
+static bool shape_valid(const rr_shape &s)
+{
+    return s.w >= 1 && s.h >= 1 && s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
+}
+
+extern "C" size_t rr_solve_workspace_bytes(rr_shape) { return 0; }
+
+extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *moves, uint32_t move_cap,
+                              uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ,
+                              rr_solve_info *info, void *workspace, size_t workspace_bytes, void *stream)
+{
+    (void)workspace; (void)workspace_bytes;
+    if (!shape_valid(shape)) return RR_E_INVAL;
+    if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
+    if (!occ || !group_off || !final_occ || !info || (move_cap > 0 && !moves)) return RR_E_INVAL;
+    if (((uintptr_t)moves & 7u) != 0) return RR_E_INVAL;
+    SolveArgs A;
+    A.W = shape.w; A.H = shape.h; A.x0 = shape.x0; A.y0 = shape.y0; A.x1 = shape.x1; A.y1 = shape.y1;
+    A.occ = occ; A.moves = moves; A.move_cap = move_cap; A.goff = group_off; A.group_cap = group_cap;
+    A.fin = final_occ; A.info = info;
+    hipStream_t st = (hipStream_t)stream;
+    const int side = shape.w > shape.h ? shape.w : shape.h;
+    if (side <= 64) hipLaunchKernelGGL(k_solve_one<64>, dim3(1), dim3(kThreads), 0, st, A);
+    else if (side <= 128) hipLaunchKernelGGL(k_solve_one<128>, dim3(1), dim3(kThreads), 0, st, A);
+    else hipLaunchKernelGGL(k_solve_one<256>, dim3(1), dim3(kThreads), 0, st, A);
+    return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
+}
+
+extern "C" rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
+                                   const uint64_t *occ_arena, rr_move *move_arena, uint32_t *group_arena,
+                                   uint64_t *final_arena, rr_solve_info *infos, void *stream)
+{
+    if (n == 0) return RR_OK;
+    if (!desc || !occ_arena || !group_arena || !final_arena || !infos || !move_arena) return RR_E_INVAL;
+    if (max_w < 1 || max_h < 1) return RR_E_INVAL;
+    if (max_w > RR_MAX_SIDE || max_h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
+    if (((uintptr_t)move_arena & 7u) != 0) return RR_E_INVAL;
+    hipStream_t st = (hipStream_t)stream;
+    const uint32_t side = max_w > max_h ? max_w : max_h;
+    if (side <= 64)
+        hipLaunchKernelGGL(k_solve_many<64>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
+                           occ_arena, move_arena, group_arena, final_arena, infos);
+    else if (side <= 128)
+        hipLaunchKernelGGL(k_solve_many<128>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
+                           occ_arena, move_arena, group_arena, final_arena, infos);
+    else
+        hipLaunchKernelGGL(k_solve_many<256>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
+                           occ_arena, move_arena, group_arena, final_arena, infos);
+    return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
+}
+
+extern "C" const char *rr_version(void) { return "librr 0.1 (gfx950)"; }

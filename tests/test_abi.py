@@ -1,0 +1,71 @@
+"""The C-ABI library loads on a CPU-only host, exports every entry point of include/rr.h, and
+rejects bad host-side arguments before any launch."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_2504_06182_amd as rr
+from paper_2504_06182_amd import build as rrbuild
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(rrbuild.LIB):
+        rrbuild.build()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rr_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("rr_solve", "rr_batch_moves", "rr_solve_many", "rr_batch_moves_many",
+              "rr_solve_workspace_bytes", "rr_batch_workspace_bytes", "rr_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", rrbuild.LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\sT\s(rr_[a-z_0-9]+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    L = rr.lib()
+    for n in declared_functions():
+        assert hasattr(L, n)
+
+
+def test_host_only_calls():
+    assert "gfx950" in rr.rr_version()
+    assert rr.rr_solve_workspace_bytes((64, 64, 10, 10, 54, 54)) == 0
+    a = rr.rr_batch_workspace_bytes((64, 64, 10, 10, 54, 54), 4000, 20000)
+    b = rr.rr_batch_workspace_bytes((64, 64, 10, 10, 54, 54), 4000, 40000)
+    assert 0 < a < b
+
+
+@pytest.mark.parametrize("shape", [(0, 4, 0, 0, 1, 1), (4, 4, 2, 0, 2, 1), (4, 4, 0, 3, 4, 5), (4, 4, 0, 0, 5, 1)])
+def test_invalid_shapes_are_rejected_before_launch(shape):
+    rc = rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, None, 0, stream=0, check=False)
+    assert rc == rr.RR_E_INVAL
+
+
+def test_oversized_grid_is_unsupported():
+    rc = rr.rr_solve((300, 300, 10, 10, 20, 20), 8, 8, 10, 8, 10, 8, 8, None, 0, stream=0, check=False)
+    assert rc == rr.RR_E_UNSUPPORTED
+
+
+def test_null_outputs_and_small_workspace_rejected():
+    shape = (32, 32, 8, 8, 24, 24)
+    assert rr.rr_solve(shape, 8, 8, 10, None, 10, 8, 8, None, 0, stream=0, check=False) == rr.RR_E_INVAL
+    assert rr.rr_solve(shape, 8, 12, 10, 8, 10, 8, 8, None, 0, stream=0, check=False) == rr.RR_E_INVAL  # misaligned
+    need = rr.rr_batch_workspace_bytes(shape, 100, 100)
+    rc = rr.rr_batch_moves(shape, 8, 8, 8, 100, 0, 8, 100, 8, 100, 8, 8, need - 1, stream=0, check=False)
+    assert rc == rr.RR_E_NOMEM
+    rc = rr.rr_batch_moves(shape, 8, 8, 8, 100, 7, 8, 100, 8, 100, 8, 8, need, stream=0, check=False)
+    assert rc == rr.RR_E_INVAL
