@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the red-rec solve + batching hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of shots already resident in HBM:
+rr_solve_many (red-rec on every shot) -> rr_plan_many (device-side arena layout from the step
+counts) -> rr_batch_moves_many (Alg. 3 on every shot), all on one stream with no host sync.
+Workload: 8192 shots of a 64x64 trap grid loaded i.i.d. Bernoulli(0.55), centred 44x44 target.
+
+Reported in one JSON line: batched shots/s (value), the 1-per-launch form (rr_solve +
+rr_batch_moves per shot) with p50/p99 latency, a bit-exact sample against the CPU oracle, the
+roofline of the dominant kernel, and the CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "red-rec shots/s batched vs 1-per-launch at 1 GPU; p50/p99 µs per shot (bit-exact)"
+WORKLOAD = "batch64"
+HBM_PEAK_GBS = 8000.0
+STEP_BOUND_PER_SHOT = 48000      # pool sizing bound for a 64x64 shot (observed ~19k steps)
+
+
+def _cpu_worker(rng):
+    """Oracle solve + batching for shots [lo, hi) of the workload (CPU baseline leg)."""
+    lo, hi = rng
+    import oracle
+    import rr_inputs as ri
+    shots = ri.config_shots(WORKLOAD, n=hi - lo, first=lo)
+    grids = [ri.shot_grid(d) for d in shots]
+    t0 = time.perf_counter()
+    for d, g in zip(shots, grids):
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        r = oracle.solve(shape, g)
+        if r["status"] == 0:
+            oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"])
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(seconds: float, max_workers: int):
+    import oracle
+    oracle.build()
+    cores = max(1, min(max_workers, os.cpu_count() or 1))
+    calib = _cpu_worker((0, 8)) / 8.0                       # seconds per shot on one core
+    per_worker = max(1, int(seconds / calib))
+    n = min(8192, per_worker * cores)
+    chunk = (n + cores - 1) // cores
+    ranges = [(i, min(n, i + chunk)) for i in range(0, n, chunk)]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(ranges)) as pool:
+        pool.map(_cpu_worker, ranges)
+    wall = time.perf_counter() - t0
+    return {"value": round(n / wall, 2), "unit": "shots/s", "cores": len(ranges), "kind": "oracle",
+            "sample": f"shots 0..{n - 1} of the same 8192-shot workload, solve + batching, "
+                      f"{len(ranges)} single-threaded oracle processes; 1-core latency {calib * 1e3:.2f} ms/shot"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--per-launch-shots", type=int, default=64)
+    ap.add_argument("--verify-shots", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-workers", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--flags", type=int, default=0, help="batching constraint (0 line-or-column, 1 along, 2 none)")
+    ap.add_argument("--traffic-gb", type=float, default=None, help="HBM bytes of one batching launch from PMC")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on exactly one GPU: this build measures the single-GPU kernel "
+              "(multi-GPU shot sharding is design-only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)      # before the GPU is touched
+
+    import numpy as np
+    import torch
+
+    import rr_inputs as ri
+    from paper_2504_06182_amd import build as rrbuild
+    if not os.path.exists(rrbuild.LIB):
+        rrbuild.build()
+    import paper_2504_06182_amd as rr
+    from paper_2504_06182_amd.pipeline import BatchBuffers, ManyBuffers, SolveBuffers
+    rr.lib()
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+
+    shots = ri.config_shots(WORKLOAD)
+    n = len(shots)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    mb = ManyBuffers(shapes, device=dev).load(grids)
+    ws_one = rr.rr_batch_workspace_bytes(shapes[0], 2 * 44 * 44, STEP_BOUND_PER_SHOT)
+    mb.alloc_pools(n * STEP_BOUND_PER_SHOT, n * (STEP_BOUND_PER_SHOT + 1), n * ((ws_one + 255) // 256 * 256))
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev: ev[0].record(stream)
+        mb.solve(stream)
+        if ev: ev[1].record(stream)
+        mb.plan_device(stream)
+        if ev: ev[2].record(stream)
+        mb.batch(args.flags, stream)
+        if ev: ev[3].record(stream)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    tot = mb.totals.cpu().numpy()
+    assert tot[0] <= mb.step_pool and tot[2] <= mb.ws_pool, "pool bound too small for this workload"
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    k_solve = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    k_plan = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    k_batch = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+
+    # results of the last timed step
+    mb.refresh_desc()
+    sinf, binf = mb.solve_infos(), mb.batch_infos()
+    sstat = sinf[:, 0].view(np.int32)
+    bstat = binf[:, 0].view(np.int32)
+    assert np.all((sstat == 0) | (sstat == 1)) and np.all(bstat == 0), "a shot failed on the GPU"
+    n_ok = int((sstat == 0).sum())
+    n_moves, n_groups, n_steps = sinf[:, 1].astype(np.int64), sinf[:, 2].astype(np.int64), sinf[:, 3].astype(np.int64)
+    n_batches = binf[:, 1].astype(np.int64)
+    ws_words = np.array([s[1] * ((s[0] + 63) // 64) for s in shapes], np.int64)
+    bytes_solve = int((16 * ws_words + 8 * n_moves + 4 * (n_groups + 1) + 24 + 80).sum())
+    bytes_batch = int((8 * n_moves + 4 * (n_groups + 1) + 24 + 80 + 4 * n_steps + 4 * (n_batches + 1) + 20).sum())
+
+    # bit-exact sample against the oracle
+    import oracle
+    oracle.build()
+    idx = np.linspace(0, n - 1, args.verify_shots).astype(int)
+    mv = mb.moves.cpu().numpy(); gr = mb.groups.cpu().numpy().view(np.uint32); fi = mb.final.cpu().numpy()
+    st = mb.steps.cpu().numpy().view(np.uint32); bo = mb.batches.cpu().numpy().view(np.uint32)
+    exact = 0
+    for i in idx:
+        g = mb.host_solve(i, sinf, mv, gr, fi)
+        r = oracle.solve(shapes[i], grids[i])
+        good = g["status"] == r["status"] and np.array_equal(g["final"], r["final"])
+        if good and r["status"] == 0:
+            good = np.array_equal(g["moves"], r["moves"]) and np.array_equal(g["group_off"], r["group_off"])
+            gb = mb.host_batch(i, binf, st, bo)
+            rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=args.flags)
+            good = good and np.array_equal(gb["batch_off"], rb["batch_off"]) and np.array_equal(gb["steps"], rb["steps"])
+        exact += int(good)
+
+    # 1-per-launch form: rr_solve + rr_batch_moves per shot, one shot at a time
+    lat = []
+    per = []
+    for i in range(min(args.per_launch_shots, n)):
+        sb = SolveBuffers(shapes[i], device=dev).load(grids[i])
+        bb = BatchBuffers(sb, step_cap=STEP_BOUND_PER_SHOT, device=dev)
+        per.append((sb, bb))
+    for sb, bb in per[:4]:
+        sb.run(stream); bb.run(args.flags, stream)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for sb, bb in per:
+        a = time.perf_counter()
+        sb.run(stream)
+        bb.run(args.flags, stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e6)
+    tp1 = time.perf_counter()
+    per_launch_sps = len(per) / (tp1 - tp0)
+    lat = np.array(lat)
+
+    value = n / (ms_per_step / 1e3)
+    achieved = bytes_batch / (k_batch / 1e3) / 1e9
+    traffic = None if args.traffic_gb is None else args.traffic_gb * 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "shots/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "8192 shots, 64x64 trap grid, i.i.d. Bernoulli(0.55) loading, centred 44x44 "
+                               "target; solve + batching (line-or-column constraint) per shot",
+                   "shots": n, "grid": [64, 64], "target": [44, 44], "p": 0.55, "flags": args.flags},
+        "kernels_ms": {"solve_many": round(k_solve, 3), "plan_many": round(k_plan, 3), "batch_many": round(k_batch, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 6),
+                     "traffic": traffic, "kernel": "k_batch_many",
+                     "algorithmic_bytes_per_launch": bytes_batch},
+        "solve_roofline": {"achieved": round(bytes_solve / (k_solve / 1e3) / 1e9, 2), "unit": "GB/s",
+                           "algorithmic_bytes_per_launch": bytes_solve},
+        "forms": {"batched_shots_per_s": round(value, 1),
+                  "per_launch_shots_per_s": round(per_launch_sps, 1),
+                  "batched_over_per_launch": round(value / per_launch_sps, 2),
+                  "per_launch_p50_us": round(float(np.percentile(lat, 50)), 1),
+                  "per_launch_p99_us": round(float(np.percentile(lat, 99)), 1),
+                  "per_launch_sample": len(lat),
+                  "batched_step_latency_us": round(ms_per_step * 1e3, 1)},
+        "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
+                           "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),
+                           "mean_batches": round(float(n_batches.mean()), 1)},
+        "bit_exact_sample": f"{exact}/{len(idx)}",
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

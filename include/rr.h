@@ -160,6 +160,17 @@ rr_status rr_batch_moves_many(uint32_t n, const rr_desc *desc, uint32_t max_w, u
                               uint32_t *batch_arena, uint32_t *step_arena, rr_batch_info *binfos,
                               void *workspace, size_t workspace_bytes, void *stream);
 
+/* Lay out the batching arenas of n solved instances on the device, with no host round trip: an
+ * exclusive scan over the instances, in order, gives instance i step_cap = batch_cap =
+ * max(1, infos[i].n_steps) (exact for an RR_OK solve) and its step_off, batch_off and ws_off in
+ * pools of step_pool uint32 steps, batch_pool uint32 batch offsets and ws_pool_bytes bytes.  An
+ * instance that does not fit gets step_cap = 0xFFFFFFFF: rr_batch_moves_many then reports
+ * RR_E_CAPACITY for it (need_steps = its step count) and writes nothing else for it.
+ * totals (device, 3 x uint64_t, may be NULL) receives the pool sizes all n instances need.
+ * desc is updated in place (shape, move_cap, group_cap and the solve offsets are kept). */
+rr_status rr_plan_many(uint32_t n, rr_desc *desc, const rr_solve_info *infos, uint64_t step_pool,
+                       uint64_t batch_pool, uint64_t ws_pool_bytes, uint64_t *totals, void *stream);
+
 /* Library version string (host). */
 const char *rr_version(void);
 

@@ -63,6 +63,7 @@ _SIGS = {
     "rr_batch_moves": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P, _SZ, _P], C.c_int),
     "rr_solve_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _P, _P, _P], C.c_int),
     "rr_batch_moves_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P], C.c_int),
+    "rr_plan_many": ([_U32, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
 }
 
 
@@ -153,6 +154,12 @@ def rr_batch_moves_many(n, desc, max_w, max_h, move_arena, group_arena, sinfos, 
                                    _ptr(step_arena), _ptr(binfos), _ptr(workspace), int(workspace_bytes),
                                    _stream(stream))
     return _check(rc, "rr_batch_moves_many") if check else rc
+
+
+def rr_plan_many(n, desc, infos, step_pool, batch_pool, ws_pool_bytes, totals=None, stream=None, check=True) -> int:
+    rc = lib().rr_plan_many(int(n), _ptr(desc), _ptr(infos), int(step_pool), int(batch_pool), int(ws_pool_bytes),
+                            _ptr(totals), _stream(stream))
+    return _check(rc, "rr_plan_many") if check else rc
 
 
 __all__ = [n for n in dir() if n.startswith("rr_") or n.startswith("RR_")] + ["lib", "RRError", "LIB_PATH"]

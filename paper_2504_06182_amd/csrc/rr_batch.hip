@@ -483,6 +483,19 @@ __global__ __launch_bounds__(kWave) void k_batch_many(const rr_desc *__restrict_
         if (threadIdx.x == 0) put_binfo(binfos + blockIdx.x, RR_E_INVAL, 0, 0, 0, 0);
         return;
     }
+    if (d.step_cap == 0xFFFFFFFFu) {
+        // the planner found no room for this instance: report the size it needs
+        if (threadIdx.x == 0) {
+            const rr_solve_info si = sinfos[blockIdx.x];
+            if (si.status == RR_INFEASIBLE || (si.status == RR_OK && si.n_moves == 0))
+                put_binfo(binfos + blockIdx.x, RR_OK, 0, 0, 0, 0);
+            else if (si.status == RR_OK)
+                put_binfo(binfos + blockIdx.x, RR_E_CAPACITY, 0, 0, si.n_steps, si.n_steps);
+            else
+                put_binfo(binfos + blockIdx.x, RR_E_INVAL, 0, 0, 0, 0);
+        }
+        return;
+    }
     BatchArgs A;
     A.W = s.w; A.H = s.h;
     A.moves = mv + d.move_off;
@@ -499,9 +512,83 @@ __global__ __launch_bounds__(kWave) void k_batch_many(const rr_desc *__restrict_
     batch_one(S, A);
 }
 
+// Arena planner: one 1024-thread workgroup scans the instances in chunks of 1024.
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan_many(uint32_t n, rr_desc *desc, const rr_solve_info *infos,
+                                                            uint64_t step_pool, uint64_t batch_pool,
+                                                            uint64_t ws_pool, uint64_t *totals)
+{
+    __shared__ uint64_t part[3][kPlanThreads / kWave];
+    __shared__ uint64_t carry[3];
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    if (tid < 3) carry[tid] = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += kPlanThreads) {
+        const uint32_t i = base + tid;
+        uint64_t v[3] = {0, 0, 0};
+        rr_desc d;
+        if (i < n) {
+            d = desc[i];
+            const rr_solve_info si = infos[i];
+            uint32_t sc = (si.status == RR_OK && si.n_steps > 0) ? si.n_steps : 1u;
+            v[0] = sc;
+            v[1] = (uint64_t)sc + 1;
+            v[2] = align256(ws_layout(d.shape.w, d.shape.h, d.move_cap, sc).total);
+        }
+        uint64_t incl[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            uint64_t x = v[q];
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const uint64_t t = shfl_u64(x, lane >= o ? lane - o : lane);
+                if (lane >= o) x += t;
+            }
+            incl[q] = x;
+            if (lane == kWave - 1) part[q][wid] = x;
+        }
+        __syncthreads();
+        uint64_t off[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            uint64_t pre = carry[q];
+            for (int w = 0; w < wid; ++w) pre += part[q][w];
+            off[q] = pre + incl[q] - v[q];
+        }
+        if (i < n) {
+            const bool fits = off[0] + v[0] <= step_pool && off[1] + v[1] <= batch_pool && off[2] + v[2] <= ws_pool;
+            d.step_cap = fits ? (uint32_t)v[0] : 0xFFFFFFFFu;
+            d.batch_cap = fits ? (uint32_t)v[0] : 0u;
+            d.step_off = fits ? off[0] : 0;
+            d.batch_off = fits ? off[1] : 0;
+            d.ws_off = fits ? off[2] : 0;
+            desc[i] = d;
+        }
+        __syncthreads();
+        if (tid < 3) {
+            uint64_t tot = 0;
+            for (int w = 0; w < kPlanThreads / kWave; ++w) tot += part[tid][w];
+            carry[tid] += tot;
+        }
+        __syncthreads();
+    }
+    if (totals && tid < 3) totals[tid] = carry[tid];
+}
+
 }  // namespace rr
 
 using namespace rr;
+
+extern "C" rr_status rr_plan_many(uint32_t n, rr_desc *desc, const rr_solve_info *infos, uint64_t step_pool,
+                                  uint64_t batch_pool, uint64_t ws_pool_bytes, uint64_t *totals, void *stream)
+{
+    if (n == 0) return RR_OK;
+    if (!desc || !infos) return RR_E_INVAL;
+    hipLaunchKernelGGL(k_plan_many, dim3(1), dim3(kPlanThreads), 0, (hipStream_t)stream, n, desc, infos, step_pool,
+                       batch_pool, ws_pool_bytes, totals);
+    return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
+}
 
 extern "C" size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step_cap)
 {

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_workspace_bytes, rr_desc, rr_solve,
+from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_workspace_bytes, rr_plan_many, rr_solve,
                rr_solve_many)
 
 SOLVE_INFO_WORDS = 6   # rr_solve_info: int32 status + 5 x uint32
@@ -196,6 +196,27 @@ class ManyBuffers:
         self.ws_bytes = ws_off
         self.ws = _dev((ws_off + 7) // 8, torch.int64, self.device)
         self.desc = torch.from_numpy(d.view(np.uint8).copy()).to(self.device)
+        return self
+
+    def alloc_pools(self, step_pool: int, batch_pool: int, ws_pool_bytes: int):
+        """Pools for the device-side planner (rr_plan_many); sizes are caller-chosen bounds."""
+        self.step_pool, self.batch_pool, self.ws_pool = int(step_pool), int(batch_pool), int(ws_pool_bytes)
+        self.steps = _dev(self.step_pool, torch.int32, self.device)
+        self.batches = _dev(self.batch_pool, torch.int32, self.device)
+        self.ws_bytes = self.ws_pool
+        self.ws = _dev((self.ws_pool + 7) // 8, torch.int64, self.device)
+        self.totals = torch.zeros(3, dtype=torch.int64, device=self.device)
+        return self
+
+    def plan_device(self, stream=None):
+        """Lay out the batching arenas on the device from the solve's step counts (no host sync)."""
+        rr_plan_many(self.n, self.desc, self.sinfo, self.step_pool, self.batch_pool, self.ws_pool, self.totals,
+                     stream)
+        return self
+
+    def refresh_desc(self):
+        """Copy the device descriptors (as updated by the planner) back to the host mirror."""
+        self.desc_np = self.desc.cpu().numpy().view(DESC_DTYPE).copy()
         return self
 
     def batch(self, flags=0, stream=None):

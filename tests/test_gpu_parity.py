@@ -250,3 +250,33 @@ def test_repeat_runs_are_identical():
         sa, sb_ = a.host_solve(i), b.host_solve(i)
         same_solve(sa, sb_, f"repeat {i}")
         same_batch(a.host_batch(i), b.host_batch(i), f"repeat {i}")
+
+
+def test_device_planner_matches_host_plan_and_reports_overflow():
+    """rr_plan_many lays out the arenas on the device; results equal the host-planned launch, and
+    instances beyond a too-small pool report RR_E_CAPACITY with their exact step count."""
+    from paper_2504_06182_amd.pipeline import ManyBuffers
+    shots = ri.config_shots("mixed", n=40)
+    say("case device planner")
+    ref, shapes, grids = run_many(shots)
+    sinf = ref.solve_infos()
+    mb = ManyBuffers(shapes).load(grids).solve()
+    mb.alloc_pools(1 << 22, 1 << 22, 1 << 30).plan_device().batch()
+    torch.cuda.synchronize()
+    mb.refresh_desc()
+    tot = mb.totals.cpu().numpy()
+    assert tot[0] == sum(max(int(i[3]), 1) if i[0] == 0 else 1 for i in sinf)
+    for i in range(len(shots)):
+        same_batch(mb.host_batch(i), ref.host_batch(i), f"planned {i}")
+    # a pool that holds only the first few instances
+    small = ManyBuffers(shapes).load(grids).solve()
+    cut = int(sum(max(int(i[3]), 1) for i in sinf[:5]))
+    small.alloc_pools(cut, 1 << 22, 1 << 30).plan_device().batch()
+    torch.cuda.synchronize()
+    small.refresh_desc()
+    binf = small.batch_infos()
+    for i in range(len(shots)):
+        if i < 5:
+            same_batch(small.host_batch(i, binf), ref.host_batch(i), f"small {i}")
+        elif sinf[i][0] == 0:
+            assert np.int32(binf[i][0]) == -2 and binf[i][4] == sinf[i][3]
