@@ -109,7 +109,11 @@ size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step
  *                                 RR_INFEASIBLE makes the batch status RR_E_INVAL, and so does a
  *                                 move off the grid, a move of length 0 or a malformed group_off).
  *   move_cap   [in]  capacity of `moves` (>= sinfo->n_moves), used to size the workspace.
- *   flags      [in]  RR_LAMBDA_*.
+ *   flags      [in]  bits 0..7: RR_LAMBDA_*; bits 8..15: LDS budget in KiB (1..56) for the loop
+ *                    state of one instance, 0 = the library's default (a tuning knob: results
+ *                    do not depend on it); bits 16..31 must be 0.
+ *                    At most 2^20 - 1 moves in at most 1024 groups (always true for rr_solve
+ *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.
  *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).
  *   steps      [out] uint32_t[step_cap]: dir << 30 | x << 15 | y, the source trap of each unit
  *                    step, dir 0 = +x, 1 = -x, 2 = +y, 3 = -y.  step_cap >= sinfo->n_steps and
@@ -153,7 +157,8 @@ rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_
                         const uint64_t *occ_arena, rr_move *move_arena, uint32_t *group_arena,
                         uint64_t *final_arena, rr_solve_info *infos, void *stream);
 
-/* Batch the moves of n solved instances in one launch (same semantics as rr_batch_moves). */
+/* Batch the moves of n solved instances in one launch (same semantics and flags as
+ * rr_batch_moves; the LDS budget in flags bits 8..15 applies to every instance). */
 rr_status rr_batch_moves_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
                               const rr_move *move_arena, const uint32_t *group_arena,
                               const rr_solve_info *sinfos, uint32_t flags,

@@ -260,18 +260,22 @@ def test_device_planner_matches_host_plan_and_reports_overflow():
     say("case device planner")
     ref, shapes, grids = run_many(shots)
     sinf = ref.solve_infos()
+    import paper_2504_06182_amd as rr
+    caps = [max(int(i[3]), 1) if i[0] == 0 else 1 for i in sinf]
+    ws_need = sum((rr.rr_batch_workspace_bytes(s, 2 * (s[4] - s[2]) * (s[5] - s[3]), c) + 255) // 256 * 256
+                  for s, c in zip(shapes, caps))
     mb = ManyBuffers(shapes).load(grids).solve()
-    mb.alloc_pools(1 << 22, 1 << 22, 1 << 30).plan_device().batch()
+    mb.alloc_pools(sum(caps), sum(caps) + len(caps), ws_need).plan_device().batch()
     torch.cuda.synchronize()
     mb.refresh_desc()
     tot = mb.totals.cpu().numpy()
-    assert tot[0] == sum(max(int(i[3]), 1) if i[0] == 0 else 1 for i in sinf)
+    assert tot[0] == sum(caps) and tot[1] == sum(caps) + len(caps) and tot[2] == ws_need
     for i in range(len(shots)):
         same_batch(mb.host_batch(i), ref.host_batch(i), f"planned {i}")
     # a pool that holds only the first few instances
     small = ManyBuffers(shapes).load(grids).solve()
-    cut = int(sum(max(int(i[3]), 1) for i in sinf[:5]))
-    small.alloc_pools(cut, 1 << 22, 1 << 30).plan_device().batch()
+    cut = int(sum(caps[:5]))
+    small.alloc_pools(cut, sum(caps) + len(caps), ws_need).plan_device().batch()
     torch.cuda.synchronize()
     small.refresh_desc()
     binf = small.batch_infos()
