@@ -64,6 +64,67 @@ def cpu_baseline(seconds: float, max_workers: int):
                       f"{len(ranges)} single-threaded oracle processes; 1-core latency {calib * 1e3:.2f} ms/shot"}
 
 
+def mixed_step_bound(shape):
+    """Pool-sizing estimate of one shot's step count (about 0.07 * side**3 for these loadings);
+    the device planner reports exact totals and the pools grow once when the estimate is short."""
+    side = max(shape[0], shape[1])
+    return int(0.08 * side ** 3) + 1024
+
+
+def mixed_graph_form(args, dev, replays):
+    """Uneven batch: 4096 shots, sides uniform over {32..256}, p ~ U[0.5, 0.65], target
+    floor(0.7 n), split by size class (one solve -> plan -> batch chain per class, each class on
+    its own stream), captured once in a HIP graph and replayed; every replay is checked against
+    the eager pass."""
+    import numpy as np
+    import torch
+
+    import rr_inputs as ri
+    from paper_2504_06182_amd.pipeline import ClassedBuffers
+    shots = ri.config_shots("mixed")
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    cb = ClassedBuffers(shapes, mixed_step_bound, device=dev).load(grids)
+    streams = [torch.cuda.Stream() for _ in cb.parts]
+    cb.run(args.flags, streams)
+    torch.cuda.synchronize()
+    if cb.fit_pools():
+        cb.run(args.flags, streams)
+        torch.cuda.synchronize()
+    ref_s, ref_b = cb.infos()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        cb.run(args.flags, streams)
+    torch.cuda.synchronize()
+    same = True
+    for _ in range(2):                         # replays, with eager reads between them
+        graph.replay()
+        torch.cuda.synchronize()
+        s_, b_ = cb.infos()
+        same = same and np.array_equal(s_, ref_s) and np.array_equal(b_, ref_b)
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        graph.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / replays
+    s_, b_ = cb.infos()
+    same = same and np.array_equal(s_, ref_s) and np.array_equal(b_, ref_b)
+    sst = s_[:, 0].view(np.int32)
+    assert np.all((sst == 0) | (sst == 1)) and np.all(b_[:, 0].view(np.int32) == 0), "a mixed shot failed"
+    ws_words = np.array([s[1] * ((s[0] + 63) // 64) for s in shapes], np.int64)
+    nm, ng, ns = s_[:, 1].astype(np.int64), s_[:, 2].astype(np.int64), s_[:, 3].astype(np.int64)
+    nbt = b_[:, 1].astype(np.int64)
+    alg = int((16 * ws_words + 8 * nm + 4 * (ng + 1) + 24 + 80).sum() +
+              (8 * nm + 4 * (ng + 1) + 24 + 80 + 4 * ns + 4 * (nbt + 1) + 20).sum())
+    return {"graph_shots_per_s": round(len(shots) / dt, 1), "graph_ms_per_replay": round(dt * 1e3, 3),
+            "graph_algorithmic_GBps": round(alg / dt / 1e9, 2), "graph_replays_equal_eager": bool(same),
+            "shots": len(shots), "infeasible": int((sst == 1).sum()),
+            "classes": {str(c): int(len(idx)) for c, idx, _ in cb.parts},
+            "workload": "4096 shots, side uniform over {32,48,64,96,128,192,256}, p ~ U[0.5,0.65], centred "
+                        "floor(0.7 n) target; one solve+plan+batch chain per size class on its own stream, "
+                        "captured in one HIP graph"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +137,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--flags", type=int, default=0, help="batching constraint (0 line-or-column, 1 along, 2 none)")
     ap.add_argument("--traffic-gb", type=float, default=None, help="HBM bytes of one batching launch from PMC")
+    ap.add_argument("--mixed-replays", type=int, default=3, help="graph replays of the uneven batch (0: skip)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the timed region, run one plain device copy of this many MiB (a known-size "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -115,8 +180,18 @@ def main():
         if ev: ev[1].record(stream)
         mb.plan_device(stream)
         if ev: ev[2].record(stream)
-        mb.batch(args.flags, stream)
-        if ev: ev[3].record(stream)
+        if ev:
+            mb.batch(args.flags, stream, graph_done_event=ev[3], loop_done_event=ev[4])
+            ev[5].record(stream)
+        else:
+            mb.batch(args.flags, stream)
+
+    if args.calib_copy_mib > 0:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(max(args.warmup, 1)):
         step()
@@ -124,7 +199,10 @@ def main():
     tot = mb.totals.cpu().numpy()
     assert tot[0] <= mb.step_pool and tot[2] <= mb.ws_pool, "pool bound too small for this workload"
 
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    for e in evs:                              # create the events the library records into
+        for x in e:
+            x.record(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -134,7 +212,10 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     k_solve = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     k_plan = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    k_batch = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    k_batch = float(np.mean([e[2].elapsed_time(e[5]) for e in evs]))
+    k_graph = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    k_loop = float(np.mean([e[3].elapsed_time(e[4]) for e in evs]))
+    k_generic = float(np.mean([e[4].elapsed_time(e[5]) for e in evs]))
 
     # results of the last timed step
     mb.refresh_desc()
@@ -188,8 +269,10 @@ def main():
     per_launch_sps = len(per) / (tp1 - tp0)
     lat = np.array(lat)
 
+    mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
+
     value = n / (ms_per_step / 1e3)
-    achieved = bytes_batch / (k_batch / 1e3) / 1e9
+    achieved = bytes_batch / (k_loop / 1e3) / 1e9
     traffic = None if args.traffic_gb is None else args.traffic_gb * 1e9
     line = {
         "metric": METRIC,
@@ -207,10 +290,12 @@ def main():
         "config": {"workload": "8192 shots, 64x64 trap grid, i.i.d. Bernoulli(0.55) loading, centred 44x44 "
                                "target; solve + batching (line-or-column constraint) per shot",
                    "shots": n, "grid": [64, 64], "target": [44, 44], "p": 0.55, "flags": args.flags},
-        "kernels_ms": {"solve_many": round(k_solve, 3), "plan_many": round(k_plan, 3), "batch_many": round(k_batch, 3)},
+        "kernels_ms": {"solve_many": round(k_solve, 3), "plan_many": round(k_plan, 3), "batch_many": round(k_batch, 3),
+                       "batch_graph": round(k_graph, 3), "batch_loop": round(k_loop, 3),
+                       "batch_generic": round(k_generic, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic, "kernel": "k_batch_many",
+                     "traffic": traffic, "kernel": "k_loop_many<3>",
                      "algorithmic_bytes_per_launch": bytes_batch},
         "solve_roofline": {"achieved": round(bytes_solve / (k_solve / 1e3) / 1e9, 2), "unit": "GB/s",
                            "algorithmic_bytes_per_launch": bytes_solve},
@@ -220,7 +305,8 @@ def main():
                   "per_launch_p50_us": round(float(np.percentile(lat, 50)), 1),
                   "per_launch_p99_us": round(float(np.percentile(lat, 99)), 1),
                   "per_launch_sample": len(lat),
-                  "batched_step_latency_us": round(ms_per_step * 1e3, 1)},
+                  "batched_step_latency_us": round(ms_per_step * 1e3, 1),
+                  "mixed_graph": mixed},
         "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
                            "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),
                            "mean_batches": round(float(n_batches.mean()), 1)},

@@ -73,6 +73,9 @@ typedef struct {
 #define RR_LAMBDA_LINE_OR_COL 0u  /* same direction, and the moving tokens share a row or a column */
 #define RR_LAMBDA_ALONG       1u  /* same direction, on one line that runs along that direction */
 #define RR_LAMBDA_NONE        2u  /* only the vertex-disjointness of Alg. 3 */
+/* Run every instance on the general batching path (no ready-set register limit; slower).  The
+ * default picks the fast path per instance and falls back to the general one by itself. */
+#define RR_BATCH_GENERIC      (1u << 16)
 
 /* Largest grid side the device kernels take. */
 #define RR_MAX_SIDE 256u
@@ -109,9 +112,10 @@ size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step
  *                                 RR_INFEASIBLE makes the batch status RR_E_INVAL, and so does a
  *                                 move off the grid, a move of length 0 or a malformed group_off).
  *   move_cap   [in]  capacity of `moves` (>= sinfo->n_moves), used to size the workspace.
- *   flags      [in]  bits 0..7: RR_LAMBDA_*; bits 8..15: LDS budget in KiB (1..56) for the loop
- *                    state of one instance, 0 = the library's default (a tuning knob: results
- *                    do not depend on it); bits 16..31 must be 0.
+ *   flags      [in]  bits 0..7: RR_LAMBDA_*; bits 8..15: LDS budget in KiB (1..255) for the loop
+ *                    data of one instance, 0 = the library's default; bit 16: RR_BATCH_GENERIC.
+ *                    Bits 8..16 are tuning and testing knobs: results do not depend on them.
+ *                    Bits 17..31 must be 0.
  *                    At most 2^20 - 1 moves in at most 1024 groups (always true for rr_solve
  *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.
  *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).
@@ -164,6 +168,19 @@ rr_status rr_batch_moves_many(uint32_t n, const rr_desc *desc, uint32_t max_w, u
                               const rr_solve_info *sinfos, uint32_t flags,
                               uint32_t *batch_arena, uint32_t *step_arena, rr_batch_info *binfos,
                               void *workspace, size_t workspace_bytes, void *stream);
+
+/* rr_batch_moves_many with its stages marked for profiling: when non-NULL, graph_done_event and
+ * loop_done_event (hipEvent_t, created by the caller) are recorded on `stream` after the graph
+ * kernel (validation and dependency graph of every instance) and after the loop kernel (Alg. 3
+ * on the fast path), so that elapsed times between them give each stage's device time.  The
+ * general-path kernel runs after loop_done_event.  Results are those of rr_batch_moves_many;
+ * a failed event record returns RR_E_DEVICE. */
+rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
+                                     const rr_move *move_arena, const uint32_t *group_arena,
+                                     const rr_solve_info *sinfos, uint32_t flags,
+                                     uint32_t *batch_arena, uint32_t *step_arena, rr_batch_info *binfos,
+                                     void *workspace, size_t workspace_bytes, void *stream,
+                                     void *graph_done_event, void *loop_done_event);
 
 /* Lay out the batching arenas of n solved instances on the device, with no host round trip: an
  * exclusive scan over the instances, in order, gives instance i step_cap = batch_cap =

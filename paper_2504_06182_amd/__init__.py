@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 RR_OK, RR_INFEASIBLE = 0, 1
 RR_E_INVAL, RR_E_CAPACITY, RR_E_DEVICE, RR_E_NOMEM, RR_E_INTERNAL, RR_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 RR_LAMBDA_LINE_OR_COL, RR_LAMBDA_ALONG, RR_LAMBDA_NONE = 0, 1, 2
+RR_BATCH_GENERIC = 1 << 16
 RR_MAX_SIDE = 256
 STATUS_NAMES = {0: "RR_OK", 1: "RR_INFEASIBLE", -1: "RR_E_INVAL", -2: "RR_E_CAPACITY", -3: "RR_E_DEVICE",
                 -4: "RR_E_NOMEM", -5: "RR_E_INTERNAL", -6: "RR_E_UNSUPPORTED"}
@@ -64,6 +65,8 @@ _SIGS = {
     "rr_solve_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _P, _P, _P], C.c_int),
     "rr_batch_moves_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "rr_plan_many": ([_U32, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
+    "rr_batch_moves_many_staged": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P, _P, _P],
+                                   C.c_int),
 }
 
 
@@ -154,6 +157,25 @@ def rr_batch_moves_many(n, desc, max_w, max_h, move_arena, group_arena, sinfos, 
                                    _ptr(step_arena), _ptr(binfos), _ptr(workspace), int(workspace_bytes),
                                    _stream(stream))
     return _check(rc, "rr_batch_moves_many") if check else rc
+
+
+def _event(e):
+    """Raw hipEvent_t of a torch.cuda.Event (created on first use), an int, or None."""
+    if e is None or isinstance(e, int):
+        return e
+    if not e.cuda_event:
+        e.record()                         # torch creates the event lazily
+    return e.cuda_event
+
+
+def rr_batch_moves_many_staged(n, desc, max_w, max_h, move_arena, group_arena, sinfos, flags, batch_arena,
+                               step_arena, binfos, workspace, workspace_bytes, stream=None, graph_done_event=None,
+                               loop_done_event=None, check=True) -> int:
+    rc = lib().rr_batch_moves_many_staged(int(n), _ptr(desc), int(max_w), int(max_h), _ptr(move_arena),
+                                          _ptr(group_arena), _ptr(sinfos), int(flags), _ptr(batch_arena),
+                                          _ptr(step_arena), _ptr(binfos), _ptr(workspace), int(workspace_bytes),
+                                          _stream(stream), _event(graph_done_event), _event(loop_done_event))
+    return _check(rc, "rr_batch_moves_many_staged") if check else rc
 
 
 def rr_plan_many(n, desc, infos, step_pool, batch_pool, ws_pool_bytes, totals=None, stream=None, check=True) -> int:

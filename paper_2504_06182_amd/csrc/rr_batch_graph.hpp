@@ -1,0 +1,458 @@
+// rr_batch_graph.hpp -- dependency graph of the batching routine (arXiv 2504.06182, §IV) for the
+// fast path: one 512-thread workgroup per instance.
+//
+// Gamma (§IV): within a group, move a precedes move b (a < b) when their paths share a trap;
+// across groups, every move of an earlier group precedes every move of a later group when the
+// two groups share a trap.  Any two moves that touch a common trap are therefore ordered, so
+// the moves touching one trap finish in index order and readiness only depends on the previous
+// toucher of each trap (the reduction the loop kernel runs on):
+//   * in-group predecessors of b: the previous toucher of each trap of b, when it is in b's
+//     group (kept once per distinct move);
+//   * group predecessors of group h: the group of the previous toucher of each trap of each
+//     move of h, when it is another group (kept once per distinct group).
+//
+// Construction, all by counting: per-trap toucher counts (atomics) -> exclusive scan ->
+// scatter of move indices -> each trap's list sorted by index -> each move walks its path and
+// looks itself up in every list it is on to find its previous toucher.  The per-trap arrays
+// live in LDS when they fit the launch's budget, else in the workspace.
+//
+// Output (workspace, read by the loop kernel): for every move its packed coordinates and a
+// 16-bit release code (no successor / exactly one successor that waits on nothing else / a
+// list), successor lists and wait counts for the general case, and per group its number of
+// group predecessors, the groups waiting on it and its head moves (no in-group predecessor).
+// The header also carries a bound on the size of the ready set: the head moves of all groups
+// plus one per extra successor of a move; the loop keeps ready sets of up to 64*S moves in
+// registers and hands instances above that to the general path.
+#pragma once
+#include "rr_device.hpp"
+#include "rr.h"
+#include "rr_batch_generic.hpp"
+
+namespace rr {
+namespace fast {
+
+constexpr uint32_t kMaxK = 65535;       // move indices fit 16 bits on the fast path
+constexpr int kMaxPreds = 8;            // distinct in-group / group predecessors of one move
+constexpr int kGT = 512;                // threads of the graph workgroup
+constexpr int kGWaves = kGT / kWave;
+constexpr int kMaxSlots = 8;            // largest register slot count of the loop kernel
+
+// release code of a move (16 bits): kind << 14 | next - b
+constexpr uint32_t kRelNone = 0, kRelNext = 1, kRelList = 2;
+constexpr uint32_t kMaxDelta = (1u << 14) - 1;
+
+// header words
+enum { H_STATE = 0, H_K, H_G, H_T, H_E, H_GE, H_HN, H_BOUND, H_NWORDS = 16 };
+// H_STATE: what the next kernel does with the instance
+enum { ST_FAST = 0, ST_DONE = 1, ST_GENERIC = 2 };
+
+struct Layout {
+    size_t hdr, mv, nx, gpend, gloff, hdoff, hd, gl, soff, sfill, slist, pend, preds, gbits, gcnt, hcnt, grp, cell,
+        touch, scratch, gen, total;
+    uint32_t Gc, GW;
+    size_t GEc;
+};
+
+__host__ __device__ inline size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// groups the fast path takes: at most W + H (every rr_solve output), 1024 and the move count
+__host__ __device__ inline uint32_t fast_group_cap(int W, int H, uint32_t move_cap)
+{
+    uint32_t g = (uint32_t)(W + H);
+    if (g > 1024u) g = 1024u;
+    if (g > move_cap) g = move_cap;
+    return g < 1u ? 1u : g;
+}
+
+__host__ __device__ inline Layout layout(int W, int H, uint32_t move_cap, uint32_t step_cap)
+{
+    Layout L;
+    const size_t K = (size_t)move_cap + 1, WH = (size_t)W * H, OCC = (size_t)move_cap + step_cap + 1;
+    L.Gc = fast_group_cap(W, H, move_cap);
+    L.GW = (L.Gc + 31) / 32;
+    L.GEc = (size_t)L.Gc * L.Gc < OCC ? (size_t)L.Gc * L.Gc : OCC;
+    size_t p = 0;
+    auto take = [&](size_t bytes) { const size_t at = p; p = al256(p + bytes); return at; };
+    L.hdr = take(4 * H_NWORDS);
+    L.mv = take(4 * K);
+    L.nx = take(2 * K);
+    L.gpend = take(2 * (size_t)L.Gc);
+    L.gloff = take(2 * ((size_t)L.Gc + 1));
+    L.hdoff = take(2 * ((size_t)L.Gc + 1));
+    L.hd = take(2 * K);
+    L.gl = take(2 * L.GEc);
+    L.soff = take(4 * (K + 1));
+    L.sfill = take(4 * K);
+    L.slist = take(4 * kMaxPreds * K);
+    L.pend = take(4 * K);
+    L.preds = take(2 * kMaxPreds * K);
+    L.gbits = take(4 * (size_t)L.Gc * L.GW);
+    L.gcnt = take(4 * ((size_t)L.Gc + 1));
+    L.hcnt = take(4 * ((size_t)L.Gc + 1));
+    L.grp = take(2 * K);
+    L.cell = take(4 * (WH + 1));
+    L.touch = take(2 * OCC);
+    L.scratch = take(16 * (size_t)kWave * kMaxSlots);
+    L.gen = p;
+    L.total = p + al256(gen::ws_layout(W, H, move_cap, step_cap).total);
+    return L;
+}
+
+// One instance of a batching call.
+struct Inst {
+    int W, H;
+    const rr_move *moves;
+    const uint32_t *goff;
+    const rr_solve_info *sinfo;
+    uint32_t move_cap, step_cap, batch_cap;
+    uint32_t *boff, *steps;
+    rr_batch_info *binfo;
+    uint8_t *ws;
+};
+
+__device__ __forceinline__ void put_info(rr_batch_info *bi, int status, uint32_t nb, uint32_t ns, uint32_t needb,
+                                         uint32_t needs)
+{
+    rr_batch_info v;
+    v.status = status; v.n_batches = nb; v.n_steps = ns; v.need_batches = needb; v.need_steps = needs;
+    *bi = v;
+}
+
+__device__ __forceinline__ void load_move(const rr_move *mv, uint32_t b, int &sx, int &sy, int &dx, int &dy)
+{
+    const uint64_t v = reinterpret_cast<const uint64_t *>(mv)[b];
+    sx = (int)(v & 0xFFFF); sy = (int)((v >> 16) & 0xFFFF); dx = (int)((v >> 32) & 0xFFFF); dy = (int)(v >> 48);
+}
+
+__device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
+
+// trap s (0..len) of the path: along row sy to column dx, then along column dx
+__device__ __forceinline__ int path_trap(int W, int sx, int sy, int dx, int dy, int s)
+{
+    const int hx = iabs(dx - sx);
+    if (s <= hx) return sy * W + (dx >= sx ? sx + s : sx - s);
+    const int v = s - hx;
+    return (dy >= sy ? sy + v : sy - v) * W + dx;
+}
+
+struct GraphShared {
+    uint32_t part[kGWaves];
+    uint32_t red[kGWaves];
+    uint32_t flags;
+};
+
+__device__ __forceinline__ uint32_t add_wg32(uint32_t *p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// workgroup sum of one value per thread (all threads get the total)
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, GraphShared &S)
+{
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    v = (uint32_t)wave_sum((int)v);
+    if (lane == 0) S.red[wid] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kGWaves; ++w) t += S.red[w];
+    __syncthreads();
+    return t;
+}
+
+// exclusive scan of a[0..n) in place, a[n] = total (a: LDS or global, visible to the workgroup)
+__device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared &S)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base <= n; base += kGT) {
+        const uint32_t i = base + tid;
+        const uint32_t v = i < n ? a[i] : 0u;
+        const uint32_t inc = (uint32_t)wave_incl_scan((int)v);
+        if (lane == kWave - 1) S.part[wid] = inc;
+        __syncthreads();
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kGWaves; ++w) {
+            const uint32_t pw = S.part[w];
+            pre += w < wid ? pw : 0u;
+            tot += pw;
+        }
+        if (i <= n) a[i] = carry + pre + inc - v;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+// sort a[0..n) ascending (distinct 16-bit values), one thread
+__device__ __forceinline__ void sort_list(uint16_t *a, int n)
+{
+    if (n <= 1) return;
+    if (n <= 16) {
+        uint32_t r[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) r[i] = i < n ? (uint32_t)a[i] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 2; k <= 16; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const bool up = (i & k) == 0;
+                        const uint32_t lo = r[i] < r[l] ? r[i] : r[l], hi = r[i] < r[l] ? r[l] : r[i];
+                        r[i] = up ? lo : hi;
+                        r[l] = up ? hi : lo;
+                    }
+                }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < n) a[i] = (uint16_t)r[i];
+        return;
+    }
+    for (int k = 1; k < n; ++k) {
+        const uint16_t v = a[k];
+        int m = k;
+        while (m > 0 && a[m - 1] > v) { a[m] = a[m - 1]; --m; }
+        a[m] = v;
+    }
+}
+
+// add v to the small distinct set s[0..n) (n <= kMaxPreds); sets ovf when it is full
+__device__ __forceinline__ void set_add(uint32_t (&s)[kMaxPreds], int &n, uint32_t v, bool &ovf)
+{
+    bool have = false;
+#pragma unroll
+    for (int i = 0; i < kMaxPreds; ++i) have |= (i < n) && s[i] == v;
+    if (have) return;
+    if (n == kMaxPreds) { ovf = true; return; }
+#pragma unroll
+    for (int i = 0; i < kMaxPreds; ++i)
+        if (i == n) s[i] = v;
+    ++n;
+}
+
+// The graph of one instance from its validated moves; cell (W*H + 1 words), grp (K) and touch
+// (K + T) are the per-trap scratch arrays.
+__device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+                                           uint32_t T, uint32_t *cell, uint16_t *grp, uint16_t *touch)
+{
+    const int tid = threadIdx.x;
+    const int W = I.W, H = I.H;
+    const uint32_t WH = (uint32_t)(W * H);
+    uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
+    uint32_t *mv32 = (uint32_t *)(I.ws + L.mv);
+    uint16_t *nx = (uint16_t *)(I.ws + L.nx);
+    uint32_t *soff = (uint32_t *)(I.ws + L.soff), *sfill = (uint32_t *)(I.ws + L.sfill);
+    uint32_t *slist = (uint32_t *)(I.ws + L.slist), *pend = (uint32_t *)(I.ws + L.pend);
+    uint16_t *preds = (uint16_t *)(I.ws + L.preds);
+    uint32_t *gbits = (uint32_t *)(I.ws + L.gbits), *gcnt = (uint32_t *)(I.ws + L.gcnt), *hcnt = (uint32_t *)(I.ws + L.hcnt);
+    const uint32_t GW = L.GW;
+
+    for (uint32_t g = tid; g < G; g += kGT)
+        for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b) grp[b] = (uint16_t)g;
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        mv32[b] = (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
+        sfill[b] = 0;
+    }
+    for (uint32_t c = tid; c <= WH; c += kGT) cell[c] = 0;
+    for (uint32_t b = tid; b <= K; b += kGT) soff[b] = 0;
+    for (uint32_t i = tid; i < G * GW; i += kGT) gbits[i] = 0;
+    if (tid == 0) S.flags = 0;
+    __syncthreads();
+
+    // ---- touch lists: count, scan, scatter (post-increment: afterwards trap c's list is
+    //      [c ? cell[c-1] : 0, cell[c]))
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const int len = iabs(dx - sx) + iabs(dy - sy);
+        for (int s = 0; s <= len; ++s) add_wg32(&cell[path_trap(W, sx, sy, dx, dy, s)], 1u);
+    }
+    __syncthreads();
+    block_scan(cell, WH, S);
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const int len = iabs(dx - sx) + iabs(dy - sy);
+        for (int s = 0; s <= len; ++s) {
+            const uint32_t at = add_wg32(&cell[path_trap(W, sx, sy, dx, dy, s)], 1u);
+            touch[at] = (uint16_t)b;
+        }
+    }
+    __syncthreads();
+    for (uint32_t c = tid; c < WH; c += kGT) {
+        const uint32_t lo = c ? cell[c - 1] : 0u;
+        sort_list(touch + lo, (int)(cell[c] - lo));
+    }
+    __syncthreads();
+
+    // ---- previous toucher of every trap of every move
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const int len = iabs(dx - sx) + iabs(dy - sy);
+        const uint32_t g = grp[b];
+        uint32_t ps[kMaxPreds], gs[kMaxPreds];
+        int np = 0, ng = 0;
+        bool ovf = false;
+        uint32_t last = 0xFFFFFFFFu;
+        for (int s = 0; s <= len; ++s) {
+            const uint32_t c = (uint32_t)path_trap(W, sx, sy, dx, dy, s);
+            uint32_t lo = c ? cell[c - 1] : 0u, hi = cell[c];
+            if (touch[lo] == b) continue;             // first toucher of this trap
+            while (hi - lo > 1) {                     // largest position with touch[pos] < b
+                const uint32_t mid = (lo + hi) >> 1;
+                if (touch[mid] < b) lo = mid; else hi = mid;
+            }
+            const uint32_t a = touch[lo];
+            if (a == last) continue;
+            last = a;
+            const uint32_t ga = grp[a];
+            if (ga == g) set_add(ps, np, a, ovf);
+            else set_add(gs, ng, ga, ovf);
+        }
+        pend[b] = (uint32_t)np;
+#pragma unroll
+        for (int i = 0; i < kMaxPreds; ++i)
+            if (i < np) { preds[(size_t)b * kMaxPreds + i] = (uint16_t)ps[i]; add_wg32(&soff[ps[i]], 1u); }
+#pragma unroll
+        for (int i = 0; i < kMaxPreds; ++i)
+            if (i < ng)
+                __hip_atomic_fetch_or(&gbits[g * GW + gs[i] / 32], 1u << (gs[i] & 31), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (ovf) S.flags = 1;
+    }
+    __syncthreads();
+    if (S.flags) {
+        if (tid == 0) hdr[H_STATE] = ST_GENERIC;
+        return;
+    }
+
+    // ---- successor lists (CSR) and release codes
+    block_scan(soff, K, S);
+    for (uint32_t b = tid; b < K; b += kGT) {
+        const uint32_t np = pend[b];
+        for (uint32_t i = 0; i < np; ++i) {
+            const uint32_t a = preds[(size_t)b * kMaxPreds + i];
+            slist[soff[a] + add_wg32(&sfill[a], 1u)] = b;
+        }
+    }
+    __syncthreads();
+    uint32_t extra = 0;
+    for (uint32_t a = tid; a < K; a += kGT) {
+        const uint32_t lo = soff[a], ns = soff[a + 1] - lo;
+        uint32_t code = kRelNone << 14;
+        if (ns == 1) {
+            const uint32_t n = slist[lo];
+            code = (pend[n] == 1u && n - a <= kMaxDelta) ? ((kRelNext << 14) | (n - a)) : (kRelList << 14);
+        } else if (ns > 1) {
+            code = kRelList << 14;
+            extra += ns - 1;
+        }
+        nx[a] = (uint16_t)code;
+    }
+    extra = block_sum(extra, S);
+
+    // ---- heads of every group, and the groups waiting on every group
+    uint16_t *gpend = (uint16_t *)(I.ws + L.gpend), *gloff = (uint16_t *)(I.ws + L.gloff);
+    uint16_t *hdoff = (uint16_t *)(I.ws + L.hdoff), *hd = (uint16_t *)(I.ws + L.hd), *gl = (uint16_t *)(I.ws + L.gl);
+    for (uint32_t g = tid; g < G; g += kGT) {
+        uint32_t c = 0;
+        for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b) c += pend[b] == 0u;
+        hcnt[g] = c;
+        uint32_t np = 0, nw = 0;
+        for (uint32_t w = 0; w < GW; ++w) np += (uint32_t)__popc(gbits[g * GW + w]);
+        for (uint32_t h = 0; h < G; ++h) nw += (gbits[h * GW + g / 32] >> (g & 31)) & 1u;
+        gpend[g] = (uint16_t)np;
+        gcnt[g] = nw;
+    }
+    __syncthreads();
+    block_scan(hcnt, G, S);
+    block_scan(gcnt, G, S);
+    for (uint32_t g = tid; g <= G; g += kGT) {
+        hdoff[g] = (uint16_t)hcnt[g];
+        gloff[g] = (uint16_t)gcnt[g];
+        if (g == G) continue;
+        uint32_t o = hcnt[g];
+        for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b)
+            if (pend[b] == 0u) hd[o++] = (uint16_t)b;
+        o = gcnt[g];
+        for (uint32_t h = 0; h < G; ++h)
+            if ((gbits[h * GW + g / 32] >> (g & 31)) & 1u) gl[o++] = (uint16_t)h;
+    }
+    if (tid == 0) {
+        const uint32_t HN = hcnt[G], GE = gcnt[G];
+        hdr[H_K] = K; hdr[H_G] = G; hdr[H_T] = T; hdr[H_E] = soff[K]; hdr[H_GE] = GE; hdr[H_HN] = HN;
+        hdr[H_BOUND] = HN + extra;
+        hdr[H_STATE] = (HN > 65535u || GE > 65535u) ? ST_GENERIC : ST_FAST;
+    }
+}
+
+// Build the graph of one instance (whole workgroup).  lds: dynamic LDS of lds_bytes bytes.
+__device__ void graph_build(const Inst &I, GraphShared &S, uint8_t *lds, uint32_t lds_bytes, bool force_generic)
+{
+    const int tid = threadIdx.x;
+    const int W = I.W, H = I.H;
+    const Layout L = layout(W, H, I.move_cap, I.step_cap);
+    uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
+    const rr_solve_info si = *I.sinfo;
+
+    // ---- trivial and invalid instances: finished here
+    if (si.status == RR_INFEASIBLE || (si.status == RR_OK && si.n_moves == 0)) {
+        if (tid == 0) { I.boff[0] = 0; put_info(I.binfo, RR_OK, 0, 0, 0, 0); hdr[H_STATE] = ST_DONE; }
+        return;
+    }
+    const uint32_t K = si.n_moves, G = si.n_groups;
+    if (si.status != RR_OK || K > I.move_cap || G > K || K > gen::kMaxMoves || G > gen::kMaxGroups) {
+        if (tid == 0) { put_info(I.binfo, RR_E_INVAL, 0, 0, 0, 0); hdr[H_STATE] = ST_DONE; }
+        return;
+    }
+    // ---- validate moves and groups; total steps
+    bool bad = false;
+    uint32_t T = 0;
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const int len = iabs(dx - sx) + iabs(dy - sy);
+        bad |= sx >= W || dx >= W || sy >= H || dy >= H || len == 0;
+        T += (uint32_t)len;
+    }
+    for (uint32_t g = tid; g < G; g += kGT) bad |= I.goff[g] > I.goff[g + 1];
+    if (tid == 0) bad |= I.goff[0] != 0 || I.goff[G] != K;
+    const uint32_t nbad = block_sum(bad ? 1u : 0u, S);
+    T = block_sum(T, S);
+    if (nbad) {
+        if (tid == 0) { put_info(I.binfo, RR_E_INVAL, 0, 0, 0, 0); hdr[H_STATE] = ST_DONE; }
+        return;
+    }
+    if (T > I.step_cap) {
+        if (tid == 0) { put_info(I.binfo, RR_E_CAPACITY, 0, 0, T, T); hdr[H_STATE] = ST_DONE; }
+        return;
+    }
+    if (force_generic || K > kMaxK || G > L.Gc) {
+        if (tid == 0) hdr[H_STATE] = ST_GENERIC;
+        return;
+    }
+
+    // ---- per-trap arrays: LDS when they fit, else the workspace (two copies of the code, so the
+    //      LDS one compiles to ds_* operations)
+    const uint32_t WH = (uint32_t)(W * H);
+    const size_t OCC = (size_t)K + T;
+    const size_t need = 4 * ((size_t)WH + 1) + 2 * (size_t)K + 2 * OCC + 16;
+    if (need <= lds_bytes) {
+        uint16_t *grp = (uint16_t *)(lds + 4 * ((size_t)WH + 1));
+        uint16_t *touch = (uint16_t *)(lds + 4 * ((size_t)WH + 1) + 2 * (((size_t)K + 1) & ~(size_t)1));
+        graph_core(I, S, L, K, G, T, (uint32_t *)lds, grp, touch);
+    } else {
+        graph_core(I, S, L, K, G, T, (uint32_t *)(I.ws + L.cell), (uint16_t *)(I.ws + L.grp),
+                   (uint16_t *)(I.ws + L.touch));
+    }
+}
+
+
+}  // namespace fast
+}  // namespace rr

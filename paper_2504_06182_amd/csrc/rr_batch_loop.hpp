@@ -1,0 +1,519 @@
+// rr_batch_loop.hpp -- the iterations of the batching routine (arXiv 2504.06182, §IV, Alg. 3)
+// on the fast path: one wave64 per instance, the ready set in registers.
+//
+// Alg. 3 takes, in each iteration, the moves whose Gamma-predecessors are all done (the ready
+// set), in ascending move index, and adds each one's next unit step to the batch when it is
+// vertex-disjoint from the steps already taken and satisfies the local constraint with each of
+// them.  Ready moves never share a trap (two that did would be ordered in Gamma), so the
+// disjointness test never rejects.  With the deployed constraint (same direction, current traps
+// on one row or one column) the batch is: the first ready move (the leader), plus every ready
+// move stepping the same way on the row or the column of the leader's trap -- whichever line
+// holds the next compatible ready move in index order.
+//
+// Ready set.  Entries sit in S register slots per lane, at positions p = 64*slot + lane, in
+// ascending move index with holes; a 64-bit mask per slot marks the valid ones.  An entry is
+// four words: current trap and direction packed as the output step code (dir << 30 | x << 15 |
+// y), the code the current leg ends on, the end code of the vertical leg still to come (or
+// none), and the key idx << 10 | group.  Batches are found with ballots: two masked compares per
+// slot give the moves on the leader's row and column, the first set bit in slot order picks
+// the line, and output positions are prefix popcounts, so the steps of a batch are written in
+// index order with one store.
+//
+// Leader runs.  When nothing ready is compatible with the leader, the leader steps alone; the
+// ready set cannot change until some move moves, so the next batches are the leader's steps
+// alone until it ends its leg or reaches the line of a waiting compatible move.  That count
+// is found with one wave-wide minimum and the batches are written in one go.
+//
+// Completions.  A finished move leaves a hole.  Its release code (LDS) gives its successor:
+// the common case -- one successor waiting on nothing else -- takes the finished move's place
+// when no ready index lies between them, else any hole between its neighbours in index order,
+// else the ready set is compacted through LDS.  General successor lists and wait counts live in
+// the workspace.  When the last move of a group finishes, the groups waiting on it are counted
+// down in parallel and the head moves of those that reach zero join the ready set.
+#pragma once
+#include "rr_batch_graph.hpp"
+
+namespace rr {
+namespace fast {
+
+constexpr uint32_t kInv = 0xFFFFFFFFu;
+constexpr uint32_t kMaskY = 0xC00001FFu;                  // direction + 9-bit row field
+constexpr uint32_t kMaskX = 0xC0000000u | (0x1FFu << 15); // direction + 9-bit column field
+
+__device__ __forceinline__ uint32_t step_delta(uint32_t d)
+{
+    return d == 0u ? (1u << 15) : (d == 1u ? (uint32_t)(-(1 << 15)) : (d == 2u ? 1u : 0xFFFFFFFFu));
+}
+
+// entry words of a move from its packed coordinates sx | sy << 8 | dx << 16 | dy << 24
+__device__ __forceinline__ void entry_of(uint32_t m, uint32_t &c, uint32_t &e, uint32_t &n)
+{
+    const uint32_t sx = m & 0xFFu, sy = (m >> 8) & 0xFFu, dx = (m >> 16) & 0xFFu, dy = m >> 24;
+    if (sx != dx) {
+        const uint32_t d = dx > sx ? 0u : 1u;
+        c = (d << 30) | (sx << 15) | sy;
+        e = (d << 30) | (dx << 15) | sy;
+        n = dy != sy ? (((dy > sy ? 2u : 3u) << 30) | (dx << 15) | dy) : kInv;
+    } else {
+        const uint32_t d = dy > sy ? 2u : 3u;
+        c = (d << 30) | (sx << 15) | sy;
+        e = (d << 30) | (dx << 15) | dy;
+        n = kInv;
+    }
+}
+
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ uint32_t wrl(uint32_t v, int l, uint32_t old) { return lane_id() == l ? v : old; }
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ int ffs64(uint64_t m) { return __ffsll((unsigned long long)m) - 1; }
+__device__ __forceinline__ int fls64(uint64_t m) { return 63 - __clzll((unsigned long long)m); }
+
+// loop data of one instance (LDS when it fits the launch's budget, else the workspace)
+struct LoopMem {
+    const uint32_t *mv;
+    const uint16_t *nx;
+    uint32_t *grem, *gpend;
+    const uint16_t *gloff, *gl, *hdoff, *hd;
+    const uint32_t *soff, *slist;
+    uint32_t *pend;
+    uint4 *scratch;
+};
+
+template <int S>
+struct Ready {
+    uint32_t c[S], e[S], n[S], k[S];
+    uint64_t vm[S];
+};
+
+template <int S>
+__device__ __forceinline__ void put_entry(Ready<S> &R, int s, int l, uint32_t c, uint32_t e, uint32_t n, uint32_t k)
+{
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+        if (i == s) {
+            R.c[i] = wrl(c, l, R.c[i]);
+            R.e[i] = wrl(e, l, R.e[i]);
+            R.n[i] = wrl(n, l, R.n[i]);
+            R.k[i] = wrl(k, l, R.k[i]);
+            R.vm[i] |= 1ull << l;
+        }
+}
+
+// Compact the ready set through LDS scratch, adding one entry at its place in index order.
+// Returns false when the set would exceed 64*S entries.
+template <int S>
+__device__ __forceinline__ bool merge_insert(Ready<S> &R, uint4 *scr, uint32_t c0, uint32_t e0, uint32_t n0, uint32_t k0)
+{
+    const int lane = lane_id();
+    uint32_t total = 1;
+#pragma unroll
+    for (int s = 0; s < S; ++s) total += (uint32_t)popc(R.vm[s]);
+    if (total > (uint32_t)(kWave * S)) return false;
+    uint32_t base = 0, nlt = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint64_t v = R.vm[s];
+        nlt += (uint32_t)popc(ballot(R.k[s] < k0) & v);
+        if ((v >> lane) & 1ull) {
+            const uint32_t r = base + mbcnt(v) + (R.k[s] > k0 ? 1u : 0u);
+            scr[r] = make_uint4(R.c[s], R.e[s], R.n[s], R.k[s]);
+        }
+        base += (uint32_t)popc(v);
+    }
+    if (lane == 0) scr[nlt] = make_uint4(c0, e0, n0, k0);
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint32_t p = (uint32_t)(s * kWave + lane);
+        const bool v = p < total;
+        const uint4 q = v ? scr[p] : make_uint4(kInv, kInv, kInv, kInv);
+        R.c[s] = q.x; R.e[s] = q.y; R.n[s] = q.z; R.k[s] = q.w;
+        R.vm[s] = ballot(v);
+    }
+    wave_sync();
+    return true;
+}
+
+// Add ready move b (group g).  (ps, pl) is the slot/lane of the move that released it (a hole
+// now) or ps < 0.  Returns false on overflow (cannot happen when the ready-set bound holds).
+template <int S>
+__device__ __forceinline__ bool insert_ready(Ready<S> &R, const LoopMem &M, uint32_t b, uint32_t g, int ps, int pl,
+                                             bool &moved)
+{
+    const int lane = lane_id();
+    uint32_t c0, e0, n0;
+    entry_of(rfl(M.mv[b]), c0, e0, n0);
+    const uint32_t k0 = (b << 10) | g;
+    int lo = -1, hi = kWave * S;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint64_t v = R.vm[s];
+        if (v) {
+            const uint64_t lt = ballot(R.k[s] < k0) & v, gt = v & ~lt;
+            if (lt) lo = s * kWave + fls64(lt);
+            if (gt && hi == kWave * S) hi = s * kWave + ffs64(gt);
+        }
+    }
+    int pos = -1;
+    if (ps >= 0) {
+        const int pp = ps * kWave + pl;
+        uint64_t hv = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (s == ps) hv = R.vm[s];
+        if (lo < pp && pp < hi && !((hv >> pl) & 1ull)) pos = pp;
+    }
+    if (pos < 0 && hi - lo > 1) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (pos >= 0) continue;
+            const int a = lo + 1 - s * kWave, z = hi - 1 - s * kWave;
+            const uint64_t holes = ~R.vm[s] & range_mask(a, z);
+            if (holes) pos = s * kWave + ffs64(holes);
+        }
+    }
+    if (pos >= 0) {
+        put_entry(R, pos / kWave, pos % kWave, c0, e0, n0, k0);
+        (void)lane;
+        return true;
+    }
+    moved = true;
+    return merge_insert(R, M.scratch, c0, e0, n0, k0);
+}
+
+// Successors of finished move b (group g) and, when b was its group's last move, the groups
+// waiting on that group.
+template <int S>
+__device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint32_t b, uint32_t g, int ps, int pl, bool &moved)
+{
+    const int lane = lane_id();
+    bool ok = true;
+    const uint32_t code = rfl(M.nx[b]);
+    const uint32_t kind = code >> 14;
+    if (kind == kRelNext) {
+        ok &= insert_ready(R, M, b + (code & kMaxDelta), g, ps, pl, moved);
+    } else if (kind == kRelList) {
+        const uint32_t lo = M.soff[b], hi = M.soff[b + 1];
+        for (uint32_t t = lo; t < hi; ++t) {
+            const uint32_t nx = M.slist[t];
+            uint32_t old = 0;
+            if (lane == 0) old = M.pend[nx]--;
+            old = rfl(old);
+            if (old == 1u) ok &= insert_ready(R, M, nx, g, ps, pl, moved);
+        }
+    }
+    uint32_t left = 0;
+    if (lane == 0) left = M.grem[g]--;
+    left = rfl(left);
+    if (left == 1u) {
+        const uint32_t lo = M.gloff[g], hi = M.gloff[g + 1];
+        for (uint32_t t0 = lo; t0 < hi; t0 += kWave) {
+            const uint32_t t = t0 + lane;
+            uint32_t h = 0;
+            bool zero = false;
+            if (t < hi) {                       // distinct groups: one lane each
+                h = M.gl[t];
+                zero = M.gpend[h]-- == 1u;
+            }
+            uint64_t zm = ballot(zero);
+            while (zm) {
+                const int l = ffs64(zm);
+                zm &= zm - 1;
+                const uint32_t hh = rdl(h, l);
+                for (uint32_t u = M.hdoff[hh]; u < M.hdoff[hh + 1]; ++u)
+                    ok &= insert_ready(R, M, M.hd[u], hh, -1, -1, moved);
+            }
+        }
+    }
+    return ok;
+}
+
+struct LoopOut {
+    uint32_t *steps, *boff;
+    uint32_t step_cap, batch_cap;
+};
+
+template <int S>
+__device__ __forceinline__ void find_leader(const Ready<S> &R, int &ls, int &ll, uint32_t &lc, uint32_t &le,
+                                            uint32_t &ln, uint32_t &lk)
+{
+    ls = -1; ll = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (ls < 0 && R.vm[s]) { ls = s; ll = ffs64(R.vm[s]); }
+    lc = le = ln = lk = kInv;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (s == ls) { lc = rdl(R.c[s], ll); le = rdl(R.e[s], ll); ln = rdl(R.n[s], ll); lk = rdl(R.k[s], ll); }
+}
+
+// Alg. 3 iterations of one instance over its loop data M.
+template <int S>
+__device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32_t K, uint32_t G, uint32_t T,
+                                         uint32_t flags)
+{
+    const int lane = lane_id();
+    // ---- initial ready set: head moves of the groups that wait on nothing, in index order
+    Ready<S> R;
+    uint32_t n0 = 0;
+    for (uint32_t g0 = 0; g0 < G; g0 += kWave) {
+        const uint32_t g = g0 + lane;
+        uint32_t cnt = 0;
+        if (g < G && M.gpend[g] == 0u) cnt = (uint32_t)(M.hdoff[g + 1] - M.hdoff[g]);
+        const uint32_t inc = (uint32_t)wave_incl_scan((int)cnt);
+        uint32_t at = n0 + inc - cnt;
+        for (uint32_t u = 0; u < cnt && at < (uint32_t)(kWave * S); ++u, ++at) {
+            const uint32_t b = M.hd[M.hdoff[g] + u];
+            uint32_t c, e, n;
+            entry_of(M.mv[b], c, e, n);
+            M.scratch[at] = make_uint4(c, e, n, (b << 10) | g);
+        }
+        n0 += (uint32_t)__shfl((int)inc, kWave - 1, kWave);
+    }
+    wave_sync();
+    bool err = n0 > (uint32_t)(kWave * S);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint32_t p = (uint32_t)(s * kWave + lane);
+        const bool v = !err && p < n0;
+        const uint4 q = v ? M.scratch[p] : make_uint4(kInv, kInv, kInv, kInv);
+        R.c[s] = q.x; R.e[s] = q.y; R.n[s] = q.z; R.k[s] = q.w;
+        R.vm[s] = ballot(v);
+    }
+    wave_sync();
+
+    uint32_t alive = err ? 0u : K, out = 0, nb = 0;
+    if (lane == 0) I.boff[0] = 0;
+    int ls, ll;
+    uint32_t lc, le, ln, lk;
+    find_leader(R, ls, ll, lc, le, ln, lk);
+
+    while (alive > 0) {
+        if (nb >= T || ls < 0) { err = true; break; }   // every batch holds a step: at most T
+        const uint32_t d1 = lc >> 30;
+        const uint32_t delta = step_delta(d1);
+        const uint64_t lbit = 1ull << ll;
+        uint64_t acc[S];
+        bool found = false;
+        if (flags == RR_LAMBDA_NONE) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) acc[s] = R.vm[s];
+            uint32_t others = 0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) others += (uint32_t)popc(R.vm[s]);
+            found = others > 1;
+        } else {
+            const uint32_t ky = lc & kMaskY, kx = lc & kMaskX;
+            const bool use_row = flags != RR_LAMBDA_ALONG || d1 < 2u;
+            const bool use_col = flags != RR_LAMBDA_ALONG || d1 >= 2u;
+            bool row = false;
+            uint64_t mr[S], mc[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                mr[s] = 0;
+                mc[s] = 0;
+                if (R.vm[s]) {
+                    if (use_row) mr[s] = ballot((R.c[s] & kMaskY) == ky);
+                    if (use_col) mc[s] = ballot((R.c[s] & kMaskX) == kx);
+                    if (s == ls) { mr[s] &= ~lbit; mc[s] &= ~lbit; }
+                    if (!found && (mr[s] | mc[s])) {
+                        found = true;
+                        row = (mr[s] >> ffs64(mr[s] | mc[s])) & 1ull;
+                    }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) acc[s] = row ? mr[s] : mc[s];
+            if (found) {
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (s == ls) acc[s] |= lbit;
+            }
+        }
+
+        uint64_t arr[S];
+        if (found) {
+            // ---- one batch: the accepted moves step, in index order
+            uint32_t base = 0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                arr[s] = 0;
+                const uint64_t a = acc[s];
+                if (a) {
+                    const bool me = (a >> lane) & 1ull;
+                    const uint32_t at = out + base + mbcnt(a);
+                    if (me) {
+                        if (at < I.step_cap) I.steps[at] = R.c[s];
+                        R.c[s] += delta;
+                    }
+                    arr[s] = ballot(me && R.c[s] == R.e[s]);
+                    base += (uint32_t)popc(a);
+                }
+            }
+            out += base;
+            ++nb;
+            if (lane == 0 && nb <= I.batch_cap) I.boff[nb] = out;
+            lc += delta;
+        } else {
+            // ---- the leader steps alone: up to its leg end or the first waiting compatible move
+            const bool horiz = d1 < 2u;
+            const uint32_t p1 = horiz ? (lc >> 15) & 0x1FFu : lc & 0x1FFu;
+            const uint32_t pe = horiz ? (le >> 15) & 0x1FFu : le & 0x1FFu;
+            const uint32_t len = p1 > pe ? p1 - pe : pe - p1;
+            uint32_t ts = len;
+            if (flags == RR_LAMBDA_LINE_OR_COL && len > 1u) {
+                uint32_t tv = len;
+                bool any = false;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    if (!R.vm[s]) continue;
+                    const uint32_t c = R.c[s];
+                    const uint32_t p = horiz ? (c >> 15) & 0x1FFu : c & 0x1FFu;
+                    const uint32_t t = (d1 & 1u) ? p1 - p : p - p1;     // wraps when behind
+                    const bool ok = (c >> 30) == d1 && t >= 1u && t < len;
+                    any |= ballot(ok) != 0ull;
+                    tv = ok && t < tv ? t : tv;
+                }
+                if (any) ts = (uint32_t)wave_min_i((int)tv);
+            }
+            for (uint32_t j = lane; j < ts; j += kWave) {
+                if (out + j < I.step_cap) I.steps[out + j] = lc + j * delta;
+                if (nb + 1 + j <= I.batch_cap) I.boff[nb + 1 + j] = out + j + 1;
+            }
+            out += ts;
+            nb += ts;
+            lc += ts * delta;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                arr[s] = 0;
+                if (s == ls) {
+                    R.c[s] = wrl(lc, ll, R.c[s]);
+                    if (ts == len) arr[s] = lbit;
+                }
+            }
+        }
+
+        // ---- legs ended: turn onto the vertical leg, or finish
+        uint64_t done[S];
+        uint32_t ndone = 0;
+        bool ldone = false;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            done[s] = 0;
+            if (arr[s]) {
+                const bool me = (arr[s] >> lane) & 1ull;
+                const bool turn = me && R.n[s] != kInv;
+                done[s] = ballot(me && !turn);
+                if (turn) {
+                    R.c[s] = (R.c[s] & 0x3FFFFFFFu) | (R.n[s] & 0xC0000000u);
+                    R.e[s] = R.n[s];
+                    R.n[s] = kInv;
+                }
+                if (s == ls && ((arr[s] >> ll) & 1ull)) {
+                    if ((done[s] >> ll) & 1ull) ldone = true;
+                    else { lc = (lc & 0x3FFFFFFFu) | (ln & 0xC0000000u); le = ln; ln = kInv; }
+                }
+                ndone += (uint32_t)popc(done[s]);
+            }
+        }
+        if (ndone == 0) continue;
+
+        // ---- finished moves leave the ready set, then release what waited on them
+        uint32_t dk[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            dk[s] = R.k[s];
+            if (done[s]) {
+                if ((done[s] >> lane) & 1ull) { R.c[s] = kInv; R.k[s] = kInv; }
+                R.vm[s] &= ~done[s];
+            }
+        }
+        alive -= ndone;
+        bool moved = false, ok = true;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            uint64_t m = done[s];
+            while (m) {
+                const int l = ffs64(m);
+                m &= m - 1;
+                const uint32_t kk = rdl(dk[s], l);
+                ok &= release_move(R, M, kk >> 10, kk & 0x3FFu, s, l, moved);
+            }
+        }
+        if (!ok) { err = true; break; }
+        if (ldone || moved) find_leader(R, ls, ll, lc, le, ln, lk);
+    }
+
+    if (lane == 0) {
+        if (err) put_info(I.binfo, RR_E_INTERNAL, 0, 0, 0, 0);
+        else if (nb > I.batch_cap) put_info(I.binfo, RR_E_CAPACITY, 0, 0, nb, T);
+        else put_info(I.binfo, RR_OK, nb, out, nb, T);
+    }
+}
+
+// Run Alg. 3 on one instance whose graph is built (header state ST_FAST, bound <= 64*S).
+template <int S>
+__device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t lds_bytes, uint32_t flags)
+{
+    const int lane = lane_id();
+    const Layout L = layout(I.W, I.H, I.move_cap, I.step_cap);
+    const uint32_t *hdr = (const uint32_t *)(I.ws + L.hdr);
+    const uint32_t K = hdr[H_K], G = hdr[H_G], T = hdr[H_T], GE = hdr[H_GE], HN = hdr[H_HN];
+
+    // ---- loop data: LDS when it fits
+    const size_t need = 16 * (size_t)kWave * S + 4 * (size_t)K + 2 * (((size_t)K + 1) & ~(size_t)1) + 8 * (size_t)G +
+                        2 * (2 * ((size_t)G + 1) + GE + HN) + 16;
+    LoopMem M;
+    M.soff = (const uint32_t *)(I.ws + L.soff);
+    M.slist = (const uint32_t *)(I.ws + L.slist);
+    M.pend = (uint32_t *)(I.ws + L.pend);
+    const uint32_t *gmv = (const uint32_t *)(I.ws + L.mv);
+    const uint16_t *gnx = (const uint16_t *)(I.ws + L.nx);
+    const uint16_t *ggp = (const uint16_t *)(I.ws + L.gpend), *ggo = (const uint16_t *)(I.ws + L.gloff);
+    const uint16_t *ghdo = (const uint16_t *)(I.ws + L.hdoff), *ghd = (const uint16_t *)(I.ws + L.hd);
+    const uint16_t *ggl = (const uint16_t *)(I.ws + L.gl);
+    if (need <= lds_bytes) {
+        uint8_t *p = lds;
+        M.scratch = (uint4 *)p; p += 16 * (size_t)kWave * S;
+        uint32_t *mv = (uint32_t *)p; p += 4 * (size_t)K;
+        uint32_t *grem = (uint32_t *)p; p += 4 * (size_t)G;
+        uint32_t *gpend = (uint32_t *)p; p += 4 * (size_t)G;
+        uint16_t *nx = (uint16_t *)p; p += 2 * (((size_t)K + 1) & ~(size_t)1);
+        uint16_t *go = (uint16_t *)p; p += 2 * ((size_t)G + 1);
+        uint16_t *hdo = (uint16_t *)p; p += 2 * ((size_t)G + 1);
+        uint16_t *gl = (uint16_t *)p; p += 2 * (size_t)GE;
+        uint16_t *hd = (uint16_t *)p;
+        for (uint32_t i = lane; i < K; i += kWave) { mv[i] = gmv[i]; nx[i] = gnx[i]; }
+        for (uint32_t i = lane; i < G; i += kWave) {
+            grem[i] = I.goff[i + 1] - I.goff[i];
+            gpend[i] = ggp[i];
+        }
+        for (uint32_t i = lane; i <= G; i += kWave) { go[i] = ggo[i]; hdo[i] = ghdo[i]; }
+        for (uint32_t i = lane; i < GE; i += kWave) gl[i] = ggl[i];
+        for (uint32_t i = lane; i < HN; i += kWave) hd[i] = ghd[i];
+        M.mv = mv; M.nx = nx; M.grem = grem; M.gpend = gpend; M.gloff = go; M.hdoff = hdo; M.gl = gl; M.hd = hd;
+        wave_sync();
+        loop_run<S>(I, M, K, G, T, flags);   // every LDS access of this copy compiles to ds_* operations
+    } else {
+        // the workspace copy; the mutable counts go to the generic path's region, which is
+        // unused on the fast path
+        uint32_t *spare = (uint32_t *)(I.ws + L.gen);
+        uint32_t *grem = spare, *gpend = spare + G;
+        for (uint32_t i = lane; i < G; i += kWave) {
+            grem[i] = I.goff[i + 1] - I.goff[i];
+            gpend[i] = ggp[i];
+        }
+        M.scratch = (uint4 *)(I.ws + L.scratch);
+        M.mv = gmv; M.nx = gnx; M.grem = grem; M.gpend = gpend; M.gloff = ggo; M.hdoff = ghdo; M.gl = ggl; M.hd = ghd;
+        wave_sync();
+        loop_run<S>(I, M, K, G, T, flags);
+    }
+}
+
+
+}  // namespace fast
+}  // namespace rr

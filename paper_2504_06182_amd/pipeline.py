@@ -8,8 +8,8 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_workspace_bytes, rr_plan_many, rr_solve,
-               rr_solve_many)
+from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_moves_many_staged, rr_batch_workspace_bytes,
+               rr_plan_many, rr_solve, rr_solve_many)
 
 SOLVE_INFO_WORDS = 6   # rr_solve_info: int32 status + 5 x uint32
 BATCH_INFO_WORDS = 5   # rr_batch_info: int32 status + 4 x uint32
@@ -219,9 +219,16 @@ class ManyBuffers:
         self.desc_np = self.desc.cpu().numpy().view(DESC_DTYPE).copy()
         return self
 
-    def batch(self, flags=0, stream=None):
-        rr_batch_moves_many(self.n, self.desc, self.max_w, self.max_h, self.moves, self.groups, self.sinfo, flags,
-                            self.batches, self.steps, self.binfo, self.ws, self.ws_bytes, stream)
+    def batch(self, flags=0, stream=None, graph_done_event=None, loop_done_event=None):
+        """Batch every solved instance; the optional events (torch.cuda.Event) mark the end of the
+        graph kernel and of the loop kernel on the stream (rr_batch_moves_many_staged)."""
+        if graph_done_event is None and loop_done_event is None:
+            rr_batch_moves_many(self.n, self.desc, self.max_w, self.max_h, self.moves, self.groups, self.sinfo,
+                                flags, self.batches, self.steps, self.binfo, self.ws, self.ws_bytes, stream)
+        else:
+            rr_batch_moves_many_staged(self.n, self.desc, self.max_w, self.max_h, self.moves, self.groups,
+                                       self.sinfo, flags, self.batches, self.steps, self.binfo, self.ws,
+                                       self.ws_bytes, stream, graph_done_event, loop_done_event)
         return self
 
     def batch_infos(self) -> np.ndarray:
@@ -261,3 +268,113 @@ class ManyBuffers:
             out["steps"] = steps[so:so + out["n_steps"]].copy()
             out["batch_off"] = batches[bo:bo + out["n_batches"] + 1].copy()
         return out
+
+
+# ------------------------------------------------------------------------------------------
+# uneven sizes: one launch chain per grid size class
+
+SIZE_CLASSES = (64, 128, 256)
+
+
+def size_class(shape) -> int:
+    """Smallest class (largest grid side it holds) for a shape: the batching launch of a class
+    picks its register slots and LDS budgets from that side."""
+    side = max(int(shape[0]), int(shape[1]))
+    for c in SIZE_CLASSES:
+        if side <= c:
+            return c
+    raise ValueError(f"grid side {side} above {SIZE_CLASSES[-1]}")
+
+
+class ClassedBuffers:
+    """Shots of uneven sizes split by size class, each class a ManyBuffers with device-planned
+    batching pools.  ``run`` enqueues solve -> plan -> batch for every class (on one stream, or
+    one stream per class), with no host synchronisation, so the whole pass can be captured in a
+    graph and replayed."""
+
+    def __init__(self, shapes, step_bound, device="cuda"):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.n = len(self.shapes)
+        self.device = device
+        by = {}
+        for i, s in enumerate(self.shapes):
+            by.setdefault(size_class(s), []).append(i)
+        self.parts = []
+        for c in SIZE_CLASSES:
+            if c not in by:
+                continue
+            idx = np.array(by[c], np.int64)
+            mb = ManyBuffers([self.shapes[i] for i in idx], device=device)
+            self.parts.append((c, idx, mb))
+        self.step_bound = step_bound
+        for _, idx, mb in self.parts:
+            self._alloc(mb, [self.step_bound(mb.shapes[k]) for k in range(mb.n)])
+
+    @staticmethod
+    def _alloc(mb, bounds):
+        steps = int(sum(max(int(b), 1) for b in bounds))
+        ws = int(sum((rr_batch_workspace_bytes(s, solve_caps(s)[0], max(int(b), 1)) + 255) // 256 * 256
+                     for s, b in zip(mb.shapes, bounds)))
+        mb.alloc_pools(steps, steps + mb.n, ws)
+
+    def load(self, grids):
+        for _, idx, mb in self.parts:
+            mb.load([grids[i] for i in idx])
+        return self
+
+    def run(self, flags=0, streams=None):
+        """Enqueue every class.  With ``streams`` the classes fork from the current stream onto
+        their own streams and join back (event edges, valid under graph capture)."""
+        if streams is None:
+            for _, _, mb in self.parts:
+                mb.solve()
+                mb.plan_device()
+                mb.batch(flags)
+            return self
+        cur = torch.cuda.current_stream()
+        for k, (_, _, mb) in enumerate(self.parts):
+            st = streams[k % len(streams)]
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                mb.solve(st)
+                mb.plan_device(st)
+                mb.batch(flags, st)
+        for k in range(min(len(streams), len(self.parts))):
+            cur.wait_stream(streams[k])
+        return self
+
+    def fit_pools(self):
+        """After a run: grow any pool the planner found too small (host sync), to the exact
+        totals it reported.  Returns True when something was reallocated (run again)."""
+        grown = False
+        for _, _, mb in self.parts:
+            tot = mb.totals.cpu().numpy()
+            if tot[0] > mb.step_pool or tot[1] > mb.batch_pool or tot[2] > mb.ws_pool:
+                mb.alloc_pools(int(tot[0]), int(tot[1]), int(tot[2]))
+                grown = True
+        return grown
+
+    def infos(self):
+        """(solve_infos, batch_infos) in the caller's shot order."""
+        s = np.zeros((self.n, SOLVE_INFO_WORDS), np.uint32)
+        b = np.zeros((self.n, BATCH_INFO_WORDS), np.uint32)
+        for _, idx, mb in self.parts:
+            s[idx] = mb.solve_infos()
+            b[idx] = mb.batch_infos()
+        return s, b
+
+    def locate(self, i):
+        for _, idx, mb in self.parts:
+            k = np.nonzero(idx == i)[0]
+            if k.size:
+                return mb, int(k[0])
+        raise IndexError(i)
+
+    def host_solve(self, i):
+        mb, k = self.locate(i)
+        return mb.host_solve(k)
+
+    def host_batch(self, i):
+        mb, k = self.locate(i)
+        mb.refresh_desc()
+        return mb.host_batch(k)

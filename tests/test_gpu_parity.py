@@ -15,6 +15,8 @@ from checker import check_batches, check_solve
 
 pytestmark = pytest.mark.gpu
 
+GENERIC = 1 << 16   # RR_BATCH_GENERIC: the general batching path for every instance
+
 torch = pytest.importorskip("torch")
 
 
@@ -108,10 +110,10 @@ def test_adversarial_solve_and_batch(name, shape, fn):
     if r["status"] == 0:
         check_solve(shape, occ, g)
         big = shape[0] * shape[1] > 130 * 130
-        for flags in ((0,) if big else (0, 1, 2)):
+        for flags in ((0,) if big else (0, 1, 2, GENERIC, 1 | GENERIC, 2 | GENERIC, 1 << 8)):
             gb = gpu_batch(sb, g["n_steps"], flags)
-            rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags)
-            same_batch(gb, rb, f"{name} flags={flags}")
+            rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF)
+            same_batch(gb, rb, f"{name} flags={flags:#x}")
             if not big:
                 check_batches(shape, occ, g["moves"], g["final"], gb["batch_off"], gb["steps"], flags)
 
@@ -284,3 +286,24 @@ def test_device_planner_matches_host_plan_and_reports_overflow():
             same_batch(small.host_batch(i, binf), ref.host_batch(i), f"small {i}")
         elif sinf[i][0] == 0:
             assert np.int32(binf[i][0]) == -2 and binf[i][4] == sinf[i][3]
+
+
+def test_fast_path_equals_general_path_and_lds_budgets():
+    """The batching paths agree byte for byte: the fast path with its loop data in LDS, the fast
+    path with its loop data in the workspace (1 KiB LDS budget) and the general path, on uneven
+    sizes and the bench grid, for every constraint; the smaller grids also against the oracle."""
+    shots = ri.config_shots("mixed", n=21) + ri.config_shots("batch64", n=6)
+    for flags in (0, 1, 2):
+        say("case paths flags", flags)
+        ref, shapes, grids = run_many(shots, flags)
+        gen, _, _ = run_many(shots, flags | GENERIC)
+        tiny, _, _ = run_many(shots, flags | (1 << 8))
+        binf = ref.batch_infos()
+        for i in range(len(shots)):
+            same_batch(gen.host_batch(i), ref.host_batch(i, binf), f"general {i} flags={flags}")
+            same_batch(tiny.host_batch(i), ref.host_batch(i, binf), f"workspace {i} flags={flags}")
+            if shapes[i][0] <= 64:
+                r = oracle.solve(shapes[i], grids[i])
+                if r["status"] == 0:
+                    rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=flags)
+                    same_batch(ref.host_batch(i, binf), rb, f"oracle {i} flags={flags}")
