@@ -125,6 +125,44 @@ def mixed_graph_form(args, dev, replays):
                         "captured in one HIP graph"}
 
 
+
+def served_form(args, dev):
+    """Served stream: Poisson arrivals at --serve-rate shots/s for --serve-seconds of the uneven
+    mix (grid side uniform over {32..256}), fed to the continuous-batching server; per-shot
+    latency = completion seen by the host - arrival."""
+    import numpy as np
+
+    import rr_inputs as ri
+    from paper_2504_06182_amd.serve import Server, poisson_arrivals, serve_stream
+    pool = ri.config_shots("mixed", n=args.serve_pool)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in pool]
+    grids = [ri.shot_grid(d) for d in pool]
+    arrivals = poisson_arrivals(args.serve_rate, args.serve_seconds, seed=50)
+    order = np.arange(len(arrivals)) % len(pool)
+    srv = Server(budget_bytes=args.serve_budget_gib << 30, max_wave=args.serve_max_wave, flags=args.flags)
+    warm = Server(budget_bytes=1 << 30, class_share={64: 0.5, 128: 0.5}, flags=args.flags)
+    for j in range(8):                               # first-launch costs outside the measurement
+        if max(shapes[j][0], shapes[j][1]) <= 128:
+            warm.submit(shapes[j], grids[j])
+    warm.drain()
+    del warm
+    wall = serve_stream(srv, shapes, grids, arrivals, order)
+    lat = srv.latencies_us()
+    per = {}
+    for side in srv.classes:
+        l_ = srv.latencies_us(side)
+        if l_.size:
+            per[str(side)] = {"n": int(l_.size), "p50_us": round(float(np.percentile(l_, 50)), 1),
+                              "p99_us": round(float(np.percentile(l_, 99)), 1)}
+    return {"served_shots_per_s": round(len(arrivals) / wall, 1), "offered_rate": args.serve_rate,
+            "shots": int(len(arrivals)), "p50_us": round(float(np.percentile(lat, 50)), 1),
+            "p99_us": round(float(np.percentile(lat, 99)), 1), "per_class": per, "waves": srv.waves,
+            "rerun_alone": srv.overflow, "slots": {str(k): v for k, v in srv.slots().items()},
+            "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s, shots cycling "
+                        f"through {len(pool)} shots of the uneven mix; continuous batching, "
+                        f"{args.serve_budget_gib} GiB of slot arenas"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +176,11 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="batching constraint (0 line-or-column, 1 along, 2 none)")
     ap.add_argument("--traffic-gb", type=float, default=None, help="HBM bytes of one batching launch from PMC")
     ap.add_argument("--mixed-replays", type=int, default=3, help="graph replays of the uneven batch (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="served stream length (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-pool", type=int, default=1024)
+    ap.add_argument("--serve-budget-gib", type=int, default=48)
+    ap.add_argument("--serve-max-wave", type=int, default=256)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one plain device copy of this many MiB (a known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
@@ -270,6 +313,7 @@ def main():
     lat = np.array(lat)
 
     mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
+    served = served_form(args, dev) if args.serve_seconds > 0 else None
 
     value = n / (ms_per_step / 1e3)
     achieved = bytes_batch / (k_loop / 1e3) / 1e9
@@ -306,7 +350,8 @@ def main():
                   "per_launch_p99_us": round(float(np.percentile(lat, 99)), 1),
                   "per_launch_sample": len(lat),
                   "batched_step_latency_us": round(ms_per_step * 1e3, 1),
-                  "mixed_graph": mixed},
+                  "mixed_graph": mixed,
+                  "served": served},
         "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
                            "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),
                            "mean_batches": round(float(n_batches.mean()), 1)},

@@ -348,7 +348,8 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
                     const uint32_t at = out + base + mbcnt(a);
                     if (me) {
                         if (at < I.step_cap) I.steps[at] = R.c[s];
-                        R.c[s] += delta;
+                        // without a constraint the batch mixes directions; else all step the leader's way
+                        R.c[s] += flags == RR_LAMBDA_NONE ? step_delta(R.c[s] >> 30) : delta;
                     }
                     arr[s] = ballot(me && R.c[s] == R.e[s]);
                     base += (uint32_t)popc(a);

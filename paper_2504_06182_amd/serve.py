@@ -1,0 +1,268 @@
+"""Continuous-batching server for red-rec shots on one GPU.
+
+Shots (a grid shape and its packed occupancy bits) arrive on the host at any time.  The server
+keeps device-resident arenas per grid size class, each cut into fixed-size *slots* (input and
+final bits, moves, group offsets, steps, batch ends, batching workspace), and admits a waiting
+shot as soon as its class has a free slot: the number of slots per class is set by a device
+memory budget (admission by memory).  Every admitted group of shots becomes one *wave*: the
+wave's grids go to the device in one copy from pinned staging and are scattered into their slots,
+then one ``rr_solve_many`` + ``rr_batch_moves_many`` pair runs over just those slots.  Each class
+has several streams and waves take them in turn, so waves overlap on the device, and shots that
+arrive while others are on the GPU are admitted as slots free up.  A wave retires when its
+completion event has fired: its shots are stamped done and their slots return to the free list.
+
+Every result is that of a single ``rr_solve`` + ``rr_batch_moves`` on the same shot: the kernels
+work per instance and are deterministic, and a slot is sized so that the shot fits (a shot whose
+step count exceeds its slot's bound is re-run alone with exact buffers, and counted).
+
+Nothing here computes any part of the method: it schedules, copies and launches.
+"""
+from __future__ import annotations
+
+import collections
+import time
+
+import numpy as np
+import torch
+
+from . import RR_E_CAPACITY, RR_OK, rr_batch_moves_many, rr_batch_workspace_bytes, rr_solve_many
+from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuffers, SolveBuffers, size_class,
+                       solve_caps, words_per_row)
+
+
+def step_bound(side: int) -> int:
+    """Steps one slot of a class holds: about twice the mean step count of the configs' loadings
+    (~0.07 * side**3), never below 4096."""
+    return max(4096, int(0.15 * side ** 3))
+
+
+class _Class:
+    """Slot arenas of one size class (largest grid side ``side``)."""
+
+    def __init__(self, side, n_slots, n_streams, device):
+        self.side = side
+        self.n = n_slots
+        full = (side, side, 0, 0, side, side)
+        self.occ_words = side * words_per_row(side)
+        self.move_cap, self.group_cap = solve_caps(full)
+        self.step_cap = step_bound(side)
+        self.ws_bytes = (rr_batch_workspace_bytes(full, self.move_cap, self.step_cap) + 255) // 256 * 256
+        n = n_slots
+        self.occ = torch.zeros(n * self.occ_words, dtype=torch.int64, device=device)
+        self.final = torch.zeros_like(self.occ)
+        self.moves = torch.empty(n * self.move_cap, dtype=torch.int64, device=device)
+        self.groups = torch.empty(n * (self.group_cap + 1), dtype=torch.int32, device=device)
+        self.steps = torch.empty(n * self.step_cap, dtype=torch.int32, device=device)
+        self.batches = torch.empty(n * (self.step_cap + 1), dtype=torch.int32, device=device)
+        self.ws = torch.empty((n * self.ws_bytes + 7) // 8, dtype=torch.int64, device=device)
+        self.free = collections.deque(range(n))
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
+        self.turn = 0
+
+    @staticmethod
+    def slot_bytes(side):
+        full = (side, side, 0, 0, side, side)
+        mc, gc = solve_caps(full)
+        sc = step_bound(side)
+        return (16 * side * words_per_row(side) + 8 * mc + 4 * (gc + 1) + 8 * sc + 4 +
+                rr_batch_workspace_bytes(full, mc, sc) + 256)
+
+
+class _Wave:
+    pass
+
+
+class Server:
+    """Continuous batching over device-resident slot arenas (see the module docstring).
+
+    ``budget_bytes``: device memory for all arenas, split over the size classes by ``class_share``
+    (fractions; a class's slot count is its share over its slot size).  ``max_wave``: most shots
+    one wave takes.  ``streams_per_class``: waves of one class in flight at once.  ``flags``:
+    batching flags.  ``keep_results``: copy every shot's outputs to the host when its wave retires
+    (for checking; off when only timing)."""
+
+    def __init__(self, budget_bytes, class_share=None, max_wave=256, streams_per_class=4, flags=0,
+                 keep_results=False, device="cuda"):
+        self.device = device
+        self.flags = int(flags)
+        self.max_wave = int(max_wave)
+        self.keep = bool(keep_results)
+        share = class_share or {64: 0.1, 128: 0.2, 256: 0.7}
+        self.classes = {}
+        for side, f in share.items():
+            n = int(budget_bytes * f) // _Class.slot_bytes(side)
+            if n > 0:
+                self.classes[side] = _Class(side, n, streams_per_class, device)
+        self.waiting = {side: collections.deque() for side in self.classes}
+        self.inflight = []
+        self.shots = []
+        self.overflow = 0
+        self.waves = 0
+
+    def slots(self):
+        return {side: c.n for side, c in self.classes.items()}
+
+    # ---- intake
+    def submit(self, shape, grid, t_arrive=None):
+        """Queue one shot (shape (w, h, x0, y0, x1, y1), packed bit rows); returns its id."""
+        shape = tuple(int(v) for v in shape)
+        side = size_class(shape)
+        if side not in self.classes:
+            raise ValueError(f"no slots for size class {side}")
+        i = len(self.shots)
+        self.shots.append(dict(shape=shape, grid=np.ascontiguousarray(grid, dtype=np.uint64).reshape(-1),
+                               t_arrive=time.perf_counter() if t_arrive is None else t_arrive, t_done=None))
+        self.waiting[side].append(i)
+        return i
+
+    # ---- one turn of the loop: admit and launch, then retire what finished
+    def pump(self):
+        launched = 0
+        for side, c in self.classes.items():
+            q = self.waiting[side]
+            while q and c.free:
+                k = min(len(q), len(c.free), self.max_wave)
+                self._launch(c, [q.popleft() for _ in range(k)], [c.free.popleft() for _ in range(k)])
+                launched += 1
+        self._retire()
+        return launched
+
+    def _launch(self, c, ids, slots):
+        n = len(ids)
+        d = np.zeros(n, DESC_DTYPE)
+        stage = torch.zeros((n, c.occ_words), dtype=torch.int64, pin_memory=True)
+        st_np = stage.numpy().view(np.uint64)
+        for k, (i, s) in enumerate(zip(ids, slots)):
+            sh = self.shots[i]
+            w, h, x0, y0, x1, y1 = sh["shape"]
+            mc, gc = solve_caps(sh["shape"])
+            d[k]["w"], d[k]["h"], d[k]["x0"], d[k]["y0"], d[k]["x1"], d[k]["y1"] = w, h, x0, y0, x1, y1
+            d[k]["move_cap"], d[k]["group_cap"] = mc, gc
+            d[k]["step_cap"], d[k]["batch_cap"] = c.step_cap, c.step_cap
+            d[k]["occ_off"] = s * c.occ_words
+            d[k]["move_off"] = s * c.move_cap
+            d[k]["group_off"] = s * (c.group_cap + 1)
+            d[k]["step_off"] = s * c.step_cap
+            d[k]["batch_off"] = s * (c.step_cap + 1)
+            d[k]["ws_off"] = s * c.ws_bytes
+            st_np[k, :sh["grid"].size] = sh["grid"]
+            sh["slot"] = s
+        desc_h = torch.from_numpy(d.view(np.uint8).copy()).pin_memory()
+        idx_h = torch.tensor(slots, dtype=torch.int64).pin_memory()
+        st = c.streams[c.turn % len(c.streams)]
+        c.turn += 1
+        w = _Wave()
+        with torch.cuda.stream(st):
+            desc = desc_h.to(self.device, non_blocking=True)
+            idx = idx_h.to(self.device, non_blocking=True)
+            rows = stage.to(self.device, non_blocking=True)
+            c.occ.view(c.n, c.occ_words).index_copy_(0, idx, rows)
+            w.sinfo = torch.empty(n * SOLVE_INFO_WORDS, dtype=torch.int32, device=self.device)
+            w.binfo = torch.empty(n * BATCH_INFO_WORDS, dtype=torch.int32, device=self.device)
+            rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo, st)
+            rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, self.flags, c.batches, c.steps,
+                                w.binfo, c.ws, c.ws.numel() * 8, st)
+            w.event = torch.cuda.Event()
+            w.event.record(st)
+        w.cls, w.ids, w.slots, w.launched = c, ids, slots, time.perf_counter()
+        w.keep_alive = (desc, idx, rows, desc_h, idx_h, stage)   # until the wave retires
+        self.inflight.append(w)
+        self.waves += 1
+
+    def _retire(self):
+        still = []
+        for w in self.inflight:
+            if not w.event.query():
+                still.append(w)
+                continue
+            now = time.perf_counter()
+            si = w.sinfo.cpu().numpy().view(np.uint32).reshape(-1, SOLVE_INFO_WORDS)
+            bi = w.binfo.cpu().numpy().view(np.uint32).reshape(-1, BATCH_INFO_WORDS)
+            for k, i in enumerate(w.ids):
+                sh = self.shots[i]
+                sh["t_launch"] = w.launched
+                if np.int32(bi[k, 0]) == RR_E_CAPACITY and np.int32(si[k, 0]) == RR_OK:
+                    self._rerun_alone(i, int(si[k, 3]))    # more steps than the slot holds
+                else:
+                    sh["sinfo"], sh["binfo"] = si[k].copy(), bi[k].copy()
+                    if self.keep:
+                        sh["out"] = self._copy_out(w.cls, w.slots[k], sh, si[k], bi[k])
+                sh["t_done"] = time.perf_counter() if self.keep else now
+            for s in w.slots:
+                w.cls.free.append(s)
+        self.inflight = still
+
+    def _copy_out(self, c, s, sh, si, bi):
+        w, h = sh["shape"][0], sh["shape"][1]
+        nw = h * words_per_row(w)
+        status = int(np.int32(si[0]))
+        sol = dict(status=status, n_moves=int(si[1]), n_groups=int(si[2]), n_steps=int(si[3]))
+        fin = c.final[s * c.occ_words:s * c.occ_words + nw].cpu().numpy().view(np.uint64)
+        sol["final"] = fin.reshape(h, words_per_row(w))
+        if status == 0:
+            mv = c.moves[s * c.move_cap:s * c.move_cap + sol["n_moves"]].cpu().numpy()
+            sol["moves"] = mv.view(np.uint16).reshape(-1, 4).copy()
+            go = c.groups[s * (c.group_cap + 1):s * (c.group_cap + 1) + sol["n_groups"] + 1].cpu().numpy()
+            sol["group_off"] = go.view(np.uint32).copy()
+        bst = int(np.int32(bi[0]))
+        bat = dict(status=bst, n_batches=int(bi[1]), n_steps=int(bi[2]))
+        if bst == 0:
+            bo = c.batches[s * (c.step_cap + 1):s * (c.step_cap + 1) + bat["n_batches"] + 1].cpu().numpy()
+            bat["batch_off"] = bo.view(np.uint32).copy()
+            sp = c.steps[s * c.step_cap:s * c.step_cap + bat["n_steps"]].cpu().numpy()
+            bat["steps"] = sp.view(np.uint32).copy()
+        return sol, bat
+
+    def _rerun_alone(self, i, n_steps):
+        self.overflow += 1
+        sh = self.shots[i]
+        sb = SolveBuffers(sh["shape"], device=self.device).load(sh["grid"]).run()
+        bb = BatchBuffers(sb, step_cap=max(n_steps, 1), device=self.device).run(self.flags)
+        torch.cuda.synchronize()
+        sol, bat = sb.host(), bb.host()
+        sh["sinfo"] = np.array([sol["status"], sol["n_moves"], sol["n_groups"], sol["n_steps"], 0, 0], np.uint32)
+        sh["binfo"] = np.array([bat["status"], bat["n_batches"], bat["n_steps"], 0, 0], np.uint32)
+        if self.keep:
+            sh["out"] = (sol, bat)
+
+    def drain(self, timeout_s=120.0):
+        t0 = time.perf_counter()
+        while any(self.waiting.values()) or self.inflight:
+            self.pump()
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")
+
+    # ---- results
+    def result(self, i):
+        """(solve, batch) of shot i as SolveBuffers.host / BatchBuffers.host give them
+        (keep_results=True)."""
+        return self.shots[i]["out"]
+
+    def latencies_us(self, side=None):
+        return np.array([(s["t_done"] - s["t_arrive"]) * 1e6 for s in self.shots
+                         if s["t_done"] is not None and (side is None or size_class(s["shape"]) == side)])
+
+
+def poisson_arrivals(rate_hz: float, duration_s: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson process: i.i.d. exponential gaps, seeded."""
+    rng = np.random.default_rng(seed)
+    n = int(rate_hz * duration_s * 1.3) + 16
+    t = np.cumsum(rng.exponential(1.0 / rate_hz, n))
+    return t[t < duration_s]
+
+
+def serve_stream(server: Server, shapes, grids, arrivals, order):
+    """Feed shots into ``server`` at their arrival times (seconds from the start) and pump until
+    all are done.  ``order[k]`` is the index into shapes/grids of the k-th arrival.  Returns the
+    wall time from the first arrival to the last completion."""
+    t0 = time.perf_counter()
+    k = 0
+    n = len(arrivals)
+    while k < n or any(server.waiting.values()) or server.inflight:
+        now = time.perf_counter() - t0
+        while k < n and arrivals[k] <= now:
+            j = order[k]
+            server.submit(shapes[j], grids[j], t_arrive=t0 + arrivals[k])
+            k += 1
+        server.pump()
+    return time.perf_counter() - t0

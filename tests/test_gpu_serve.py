@@ -1,0 +1,95 @@
+"""Served form: continuous batching returns, for every shot, exactly what a single-instance launch
+returns, whatever else is in flight -- and the oracle's result for the grids it finishes quickly."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu_ready():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_06182_amd
+    paper_2504_06182_amd.lib()
+    torch.cuda.set_device(0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def alone(shape, grid, flags=0):
+    from paper_2504_06182_amd.pipeline import BatchBuffers, SolveBuffers
+    sb = SolveBuffers(shape).load(grid).run()
+    torch.cuda.synchronize()
+    g = sb.host()
+    bb = BatchBuffers(sb, step_cap=max(g["n_steps"], 1)).run(flags)
+    torch.cuda.synchronize()
+    return g, bb.host()
+
+
+def same(a, b, tag):
+    (sa, ba), (sb, bb) = a, b
+    assert sa["status"] == sb["status"], tag
+    assert np.array_equal(sa["final"], sb["final"]), tag
+    if sa["status"] == 0:
+        assert np.array_equal(sa["moves"], sb["moves"]), tag
+        assert np.array_equal(sa["group_off"], sb["group_off"]), tag
+        assert ba["status"] == bb["status"] == 0, tag
+        assert np.array_equal(ba["batch_off"], bb["batch_off"]), tag
+        assert np.array_equal(ba["steps"], bb["steps"]), tag
+
+
+def test_served_results_equal_alone_and_oracle():
+    from paper_2504_06182_amd.serve import Server
+    shots = ri.config_shots("mixed", n=70)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    say("case served mix", len(shots))
+    srv = Server(budget_bytes=6 << 30, max_wave=8, keep_results=True)
+    peak = 0
+    for k in range(len(shots)):                # arrivals interleaved with the device's work
+        srv.submit(shapes[k], grids[k])
+        if k % 3 == 2:
+            srv.pump()
+            peak = max(peak, len(srv.inflight))
+    srv.drain()
+    assert peak >= 2, "waves never overlapped"
+    for i in range(len(shots)):
+        a = alone(shapes[i], grids[i])
+        same(srv.result(i), a, f"served {i} {shapes[i]}")
+        if shapes[i][0] <= 64:
+            r = oracle.solve(shapes[i], grids[i])
+            assert a[0]["status"] == r["status"]
+            if r["status"] == 0:
+                assert np.array_equal(a[0]["moves"], r["moves"])
+                rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"])
+                assert np.array_equal(a[1]["steps"], rb["steps"])
+                assert np.array_equal(a[1]["batch_off"], rb["batch_off"])
+
+
+def test_served_admission_under_a_tiny_budget():
+    """A budget of a few slots: shots wait for free slots, none is lost, results unchanged."""
+    from paper_2504_06182_amd.serve import Server, _Class
+    shots = ri.config_shots("batch64", n=24)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    say("case served tiny budget")
+    srv = Server(budget_bytes=3 * _Class.slot_bytes(64), class_share={64: 1.0}, max_wave=4, keep_results=True)
+    assert srv.slots() == {64: 3}
+    for k in range(len(shots)):
+        srv.submit(shapes[k], grids[k])
+    srv.drain()
+    assert srv.waves >= 8
+    for i in range(len(shots)):
+        same(srv.result(i), alone(shapes[i], grids[i]), f"tiny {i}")
