@@ -32,7 +32,7 @@ namespace rr {
 namespace fast {
 
 constexpr uint32_t kMaxK = 65535;       // move indices fit 16 bits on the fast path
-constexpr int kMaxPreds = 8;            // distinct in-group / group predecessors of one move
+constexpr int kMaxPreds = 8;            // distinct in-group predecessors of one move
 constexpr int kGT = 512;                // threads of the graph workgroup
 constexpr int kGWaves = kGT / kWave;
 constexpr int kMaxSlots = 8;            // largest register slot count of the loop kernel
@@ -296,10 +296,10 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
         load_move(I.moves, b, sx, sy, dx, dy);
         const int len = iabs(dx - sx) + iabs(dy - sy);
         const uint32_t g = grp[b];
-        uint32_t ps[kMaxPreds], gs[kMaxPreds];
-        int np = 0, ng = 0;
+        uint32_t ps[kMaxPreds];
+        int np = 0;
         bool ovf = false;
-        uint32_t last = 0xFFFFFFFFu;
+        uint32_t last = 0xFFFFFFFFu, lastg = 0xFFFFFFFFu;
         for (int s = 0; s <= len; ++s) {
             const uint32_t c = (uint32_t)path_trap(W, sx, sy, dx, dy, s);
             uint32_t lo = c ? cell[c - 1] : 0u, hi = cell[c];
@@ -312,18 +312,18 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
             if (a == last) continue;
             last = a;
             const uint32_t ga = grp[a];
-            if (ga == g) set_add(ps, np, a, ovf);
-            else set_add(gs, ng, ga, ovf);
+            if (ga == g) {
+                set_add(ps, np, a, ovf);
+            } else if (ga != lastg) {        // a group predecessor: the bit matrix keeps it once
+                lastg = ga;
+                __hip_atomic_fetch_or(&gbits[g * GW + ga / 32], 1u << (ga & 31), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
         pend[b] = (uint32_t)np;
 #pragma unroll
         for (int i = 0; i < kMaxPreds; ++i)
             if (i < np) { preds[(size_t)b * kMaxPreds + i] = (uint16_t)ps[i]; add_wg32(&soff[ps[i]], 1u); }
-#pragma unroll
-        for (int i = 0; i < kMaxPreds; ++i)
-            if (i < ng)
-                __hip_atomic_fetch_or(&gbits[g * GW + gs[i] / 32], 1u << (gs[i] & 31), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_WORKGROUP);
         if (ovf) S.flags = 1;
     }
     __syncthreads();
