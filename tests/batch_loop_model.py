@@ -1,0 +1,299 @@
+"""Lane-level CPU model of the fast batching path (the graph kernel and the register-resident
+loop kernel), written statement by statement after the HIP code: 64 lanes x S register slots,
+ballots as bit masks, the leader cache in scalars.  Test infrastructure: it lets the CPU suite
+check the fast path's logic (leader runs, holes, in-place successors, compaction, the
+ready-set bound) against the oracle without a GPU; the GPU tests check the kernels themselves.
+"""
+import numpy as np
+
+INV = 0xFFFFFFFF; MY = 0xC00001FF; MX = 0xC0000000 | (0x1FF << 15); M32 = 0xFFFFFFFF
+W64 = 64
+def delta_of(d): return [1 << 15, (-(1 << 15)) & M32, 1, 0xFFFFFFFF][d]
+def entry_of(m):
+    sx, sy, dx, dy = m & 0xFF, (m >> 8) & 0xFF, (m >> 16) & 0xFF, m >> 24
+    if sx != dx:
+        d = 0 if dx > sx else 1
+        return (d << 30) | (sx << 15) | sy, (d << 30) | (dx << 15) | sy, ((((2 if dy > sy else 3) << 30) | (dx << 15) | dy) if dy != sy else INV)
+    d = 2 if dy > sy else 3
+    return (d << 30) | (sx << 15) | sy, (d << 30) | (dx << 15) | dy, INV
+def ballot(v): return int(sum((1 << l) for l in range(64) if v[l]))
+def ffs(m): return (m & -m).bit_length() - 1
+def fls(m): return m.bit_length() - 1
+def popc(m): return bin(m).count('1')
+def range_mask(lo, hi):
+    if hi < lo or hi < 0 or lo > 63: return 0
+    lo = max(lo, 0); hi = min(hi, 63)
+    return ((1 << (hi + 1)) - 1) & ~((1 << lo) - 1)
+
+class R:
+    def __init__(s, S):
+        s.S = S
+        s.c = [[INV] * 64 for _ in range(S)]; s.e = [[INV] * 64 for _ in range(S)]
+        s.n = [[INV] * 64 for _ in range(S)]; s.k = [[INV] * 64 for _ in range(S)]; s.vm = [0] * S
+
+def merge_insert(Rr, c0, e0, n0, k0, scr):
+    S = Rr.S
+    total = 1 + sum(popc(v) for v in Rr.vm)
+    if total > 64 * S: return False
+    base = 0; nlt = 0
+    for s in range(S):
+        v = Rr.vm[s]
+        nlt += popc(ballot([Rr.k[s][l] < k0 for l in range(64)]) & v)
+        for l in range(64):
+            if (v >> l) & 1:
+                r = base + popc(v & ((1 << l) - 1)) + (1 if Rr.k[s][l] > k0 else 0)
+                scr[r] = (Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l])
+        base += popc(v)
+    scr[nlt] = (c0, e0, n0, k0)
+    for s in range(S):
+        for l in range(64):
+            p = s * 64 + l
+            q = scr[p] if p < total else (INV, INV, INV, INV)
+            Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l] = q
+        Rr.vm[s] = ballot([s * 64 + l < total for l in range(64)])
+    return True
+
+def insert_ready(Rr, Gd, b, g, ps, pl, st, scr):
+    S = Rr.S
+    c0, e0, n0 = entry_of(Gd['mv'][b]); k0 = (b << 10) | g
+    lo, hi = -1, 64 * S
+    for s in range(S):
+        v = Rr.vm[s]
+        if v:
+            lt = ballot([Rr.k[s][l] < k0 for l in range(64)]) & v; gt = v & ~lt
+            if lt: lo = s * 64 + fls(lt)
+            if gt and hi == 64 * S: hi = s * 64 + ffs(gt)
+    pos = -1
+    if ps >= 0:
+        pp = ps * 64 + pl
+        if lo < pp < hi and not ((Rr.vm[ps] >> pl) & 1): pos = pp
+    if pos < 0 and hi - lo > 1:
+        for s in range(S):
+            if pos >= 0: continue
+            holes = ~Rr.vm[s] & range_mask(lo + 1 - s * 64, hi - 1 - s * 64) & ((1 << 64) - 1)
+            if holes: pos = s * 64 + ffs(holes)
+    if pos >= 0:
+        s, l = divmod(pos, 64)
+        Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l] = c0, e0, n0, k0; Rr.vm[s] |= 1 << l
+        st['inplace' if pos == (ps * 64 + pl if ps >= 0 else -9) else 'hole'] += 1
+        return True
+    st['moved'] = True; st['merge'] += 1
+    return merge_insert(Rr, c0, e0, n0, k0, scr)
+
+def release_move(Rr, Gd, b, g, ps, pl, st, scr, grem, gpend, pend):
+    ok = True
+    code = Gd['nx'][b]; kind = code >> 14
+    if kind == 1: ok &= insert_ready(Rr, Gd, b + (code & 16383), g, ps, pl, st, scr)
+    elif kind == 2:
+        for nxm in Gd['succ'][b]:
+            old = pend[nxm]; pend[nxm] -= 1
+            if old == 1: ok &= insert_ready(Rr, Gd, nxm, g, ps, pl, st, scr)
+    left = grem[g]; grem[g] -= 1
+    if left == 1:
+        for h in sorted(Gd['gw'][g]):
+            old = gpend[h]; gpend[h] -= 1
+            if old == 1:
+                for hb in Gd['heads'][h]: ok &= insert_ready(Rr, Gd, hb, h, -1, -1, st, scr)
+    return ok
+
+def find_leader(Rr):
+    for s in range(Rr.S):
+        if Rr.vm[s]:
+            l = ffs(Rr.vm[s]); return s, l, Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l]
+    return -1, 0, INV, INV, INV, INV
+
+def loop(Gd, S, flags):
+    K, G = Gd['K'], Gd['G']
+    T = sum(abs(((m >> 16) & 0xFF) - (m & 0xFF)) + abs((m >> 24) - ((m >> 8) & 0xFF)) for m in Gd['mv'])
+    grem = [Gd['goff'][g + 1] - Gd['goff'][g] for g in range(G)]
+    gpend = list(Gd['gpend']); pend = list(Gd['pend'])
+    scr = [None] * (64 * S)
+    Rr = R(S)
+    ents = []
+    for g in range(G):
+        if gpend[g] == 0:
+            for b in Gd['heads'][g]:
+                c, e, n = entry_of(Gd['mv'][b]); ents.append((c, e, n, (b << 10) | g))
+    assert len(ents) <= 64 * S
+    for p, q in enumerate(ents):
+        s, l = divmod(p, 64); Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l] = q; Rr.vm[s] |= 1 << l
+    st = dict(inplace=0, hole=0, merge=0, moved=False, iters=0, bulk=0)
+    alive = K; out = 0; nb = 0; steps = []; boff = [0]
+    ls, ll, lc, le, ln, lk = find_leader(Rr)
+    while alive > 0:
+        if nb >= T or ls < 0: raise RuntimeError('err')
+        d1 = lc >> 30; delta = delta_of(d1); lbit = 1 << ll
+        acc = [0] * S; found = False
+        if flags == 2:
+            acc = list(Rr.vm); found = sum(popc(v) for v in Rr.vm) > 1
+        else:
+            ky, kx = lc & MY, lc & MX
+            use_row = flags != 1 or d1 < 2; use_col = flags != 1 or d1 >= 2
+            row = False; mr = [0] * S; mc = [0] * S
+            for s in range(S):
+                if Rr.vm[s]:
+                    if use_row: mr[s] = ballot([(Rr.c[s][l] & MY) == ky for l in range(64)])
+                    if use_col: mc[s] = ballot([(Rr.c[s][l] & MX) == kx for l in range(64)])
+                    if s == ls: mr[s] &= ~lbit; mc[s] &= ~lbit
+                    if not found and (mr[s] | mc[s]):
+                        found = True; row = bool((mr[s] >> ffs(mr[s] | mc[s])) & 1)
+            acc = [mr[s] if row else mc[s] for s in range(S)]
+            if found: acc[ls] |= lbit
+        arr = [0] * S
+        if found:
+            st['iters'] += 1
+            base = 0
+            for s in range(S):
+                a = acc[s]
+                if a:
+                    me = [(a >> l) & 1 for l in range(64)]
+                    for l in range(64):
+                        if me[l]:
+                            at = out + base + popc(a & ((1 << l) - 1))
+                            assert at == len(steps); steps.append(Rr.c[s][l])
+                            Rr.c[s][l] = (Rr.c[s][l] + (delta_of(Rr.c[s][l] >> 30) if flags == 2 else delta)) & M32
+                    arr[s] = ballot([me[l] and Rr.c[s][l] == Rr.e[s][l] for l in range(64)])
+                    base += popc(a)
+            out += base; nb += 1; boff.append(out); lc = (lc + delta) & M32
+        else:
+            st['bulk'] += 1
+            horiz = d1 < 2
+            p1 = (lc >> 15) & 0x1FF if horiz else lc & 0x1FF
+            pe = (le >> 15) & 0x1FF if horiz else le & 0x1FF
+            ln_ = abs(p1 - pe); ts = ln_
+            if flags == 0 and ln_ > 1:
+                tv = [ln_] * 64; anyok = False
+                for s in range(S):
+                    if not Rr.vm[s]: continue
+                    oks = []
+                    for l in range(64):
+                        c = Rr.c[s][l]
+                        p = (c >> 15) & 0x1FF if horiz else c & 0x1FF
+                        t = ((p1 - p) if (d1 & 1) else (p - p1)) & M32
+                        ok = (c >> 30) == d1 and 1 <= t < ln_
+                        oks.append(ok)
+                        if ok and t < tv[l]: tv[l] = t
+                    anyok |= ballot(oks) != 0
+                if anyok: ts = min(tv)
+            for j in range(ts):
+                steps.append((lc + j * delta) & M32); boff.append(out + j + 1)
+            out += ts; nb += ts; lc = (lc + ts * delta) & M32
+            Rr.c[ls][ll] = lc
+            if ts == ln_: arr[ls] = lbit
+        done = [0] * S; ndone = 0; ldone = False
+        for s in range(S):
+            if arr[s]:
+                me = [(arr[s] >> l) & 1 for l in range(64)]
+                turn = [me[l] and Rr.n[s][l] != INV for l in range(64)]
+                done[s] = ballot([me[l] and not turn[l] for l in range(64)])
+                for l in range(64):
+                    if turn[l]:
+                        Rr.c[s][l] = (Rr.c[s][l] & 0x3FFFFFFF) | (Rr.n[s][l] & 0xC0000000); Rr.e[s][l] = Rr.n[s][l]; Rr.n[s][l] = INV
+                if s == ls and (arr[s] >> ll) & 1:
+                    if (done[s] >> ll) & 1: ldone = True
+                    else: lc = (lc & 0x3FFFFFFF) | (ln & 0xC0000000); le = ln; ln = INV
+                ndone += popc(done[s])
+        if ndone == 0: continue
+        dk = [list(Rr.k[s]) for s in range(S)]
+        for s in range(S):
+            if done[s]:
+                for l in range(64):
+                    if (done[s] >> l) & 1: Rr.c[s][l] = INV; Rr.k[s][l] = INV
+                Rr.vm[s] &= ~done[s]
+        alive -= ndone
+        st['moved'] = False; ok = True
+        for s in range(S):
+            m = done[s]
+            while m:
+                l = ffs(m); m &= m - 1
+                kk = dk[s][l]
+                ok &= release_move(Rr, Gd, kk >> 10, kk & 0x3FF, s, l, st, scr, grem, gpend, pend)
+        if not ok: raise RuntimeError('overflow')
+        if ldone or st['moved']: ls, ll, lc, le, ln, lk = find_leader(Rr)
+        else:
+            # the cached leader must still match its lane
+            assert Rr.c[ls][ll] == lc and Rr.e[ls][ll] == le and Rr.n[ls][ll] == ln, 'leader cache'
+    return np.array(boff, np.uint32), np.array(steps, np.uint32), st
+
+
+def graph(shape, moves, goff):
+    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other."""
+    W, H = shape[0], shape[1]
+    K = len(moves); G = len(goff) - 1; WH = W * H
+    mvs = [tuple(int(v) for v in m) for m in moves]
+    def trap(m, s):
+        sx, sy, dx, dy = m
+        hx = abs(dx - sx)
+        if s <= hx: return sy * W + (sx + s if dx >= sx else sx - s)
+        v = s - hx
+        return (sy + v if dy >= sy else sy - v) * W + dx
+    L = lambda m: abs(m[2] - m[0]) + abs(m[3] - m[1])
+    grp = [0] * K
+    for g in range(G):
+        for b in range(goff[g], goff[g + 1]): grp[b] = g
+    cell = [0] * (WH + 1)
+    for b in range(K):
+        for s in range(L(mvs[b]) + 1): cell[trap(mvs[b], s)] += 1
+    run = 0
+    for c in range(WH + 1):
+        v = cell[c] if c < WH else 0
+        cell[c] = run; run += v
+    touch = [None] * (cell[WH])
+    # scatter in an arbitrary thread order (reverse) to mimic atomics
+    for b in reversed(range(K)):
+        for s in range(L(mvs[b]) + 1):
+            c = trap(mvs[b], s); touch[cell[c]] = b; cell[c] += 1
+    for c in range(WH):
+        lo = cell[c - 1] if c else 0
+        touch[lo:cell[c]] = sorted(touch[lo:cell[c]])
+    pend = [0] * K; preds = [[] for _ in range(K)]; soff = [0] * (K + 1); gbits = {}
+    ovf = False
+    for b in range(K):
+        g = grp[b]; ps = []; gs = []; last = None
+        for s in range(L(mvs[b]) + 1):
+            c = trap(mvs[b], s)
+            lo = cell[c - 1] if c else 0; hi = cell[c]
+            if touch[lo] == b: continue
+            while hi - lo > 1:
+                mid = (lo + hi) >> 1
+                if touch[mid] < b: lo = mid
+                else: hi = mid
+            a = touch[lo]
+            if a == last: continue
+            last = a
+            if grp[a] == g:
+                if a not in ps:
+                    if len(ps) == 8: ovf = True
+                    else: ps.append(a)
+            else:
+                if grp[a] not in gs: gs.append(grp[a])
+        pend[b] = len(ps); preds[b] = ps
+        for a in ps: soff[a] += 1
+        for x in gs: gbits.setdefault(g, set()).add(x)
+    assert not ovf
+    run = 0
+    for a in range(K + 1):
+        v = soff[a] if a < K else 0
+        soff[a] = run; run += v
+    slist = [None] * soff[K]; fill = [0] * K
+    for b in reversed(range(K)):
+        for a in preds[b]:
+            slist[soff[a] + fill[a]] = b; fill[a] += 1
+    nx = []; extra = 0
+    for a in range(K):
+        lo, ns = soff[a], soff[a + 1] - soff[a]
+        code = 0
+        if ns == 1:
+            n = slist[lo]
+            code = ((1 << 14) | (n - a)) if (pend[n] == 1 and n - a <= 16383) else (2 << 14)
+        elif ns > 1:
+            code = 2 << 14; extra += ns - 1
+        nx.append(code)
+    heads = [[b for b in range(goff[g], goff[g + 1]) if pend[b] == 0] for g in range(G)]
+    gpend = [len(gbits.get(g, ())) for g in range(G)]
+    gw = [[h for h in range(G) if g in gbits.get(h, ())] for g in range(G)]
+    succ = [slist[soff[a]:soff[a + 1]] for a in range(K)]
+    mv = [m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24) for m in mvs]
+    HN = sum(len(h) for h in heads)
+    return dict(K=K, G=G, mv=mv, nx=nx, succ=succ, pend=pend, gw=gw, gpend=gpend, heads=heads,
+                bound=HN + extra, goff=list(goff))

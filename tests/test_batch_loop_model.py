@@ -1,0 +1,49 @@
+"""The lane-level CPU model of the fast batching path (tests/batch_loop_model.py) reproduces the
+oracle's batches bit for bit under every constraint, and its ready set stays within the bound the
+graph reports -- the logic the GPU kernels run, checked without a GPU."""
+import numpy as np
+import pytest
+
+import batch_loop_model as M
+import oracle
+import rr_inputs as ri
+
+
+def _cases():
+    out = []
+    for name, n in (("single32", 2), ("batch64", 2), ("mixed", 12)):
+        for d in ri.config_shots(name, n=n):
+            if d["w"] <= 64:
+                out.append((name, d))
+    return out
+
+
+@pytest.mark.parametrize("name,d", _cases(), ids=lambda v: v if isinstance(v, str) else f"shot{v['shot']}")
+def test_model_matches_oracle(name, d):
+    shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+    r = oracle.solve(shape, ri.shot_grid(d))
+    assert r["status"] == 0
+    g = M.graph(shape, r["moves"], r["group_off"])
+    S = 3
+    assert g["bound"] <= 64 * S
+    for flags in (0, 1, 2):
+        b = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags)
+        pb, ps, st = M.loop(g, S, flags)
+        assert np.array_equal(pb, b["batch_off"]), (name, flags)
+        assert np.array_equal(ps, b["steps"]), (name, flags)
+        if flags == 0:
+            assert st["bulk"] > 0 and st["inplace"] > 0
+
+
+def test_model_compaction_path():
+    """With few register slots the ready set fills up and the model compacts it (merge path);
+    results stay the oracle's."""
+    d = ri.config_shots("single32", n=1)[0]
+    shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+    r = oracle.solve(shape, ri.shot_grid(d))
+    g = M.graph(shape, r["moves"], r["group_off"])
+    S = 1
+    assert g["bound"] <= 64 * S
+    b = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=2)
+    pb, ps, st = M.loop(g, S, 2)
+    assert np.array_equal(pb, b["batch_off"]) and np.array_equal(ps, b["steps"])
