@@ -197,9 +197,9 @@ __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint
     if (kind == kRelNext) {
         ok &= insert_ready(R, M, b + (code & kMaxDelta), g, ps, pl, moved);
     } else if (kind == kRelList) {
-        const uint32_t lo = M.soff[b], hi = M.soff[b + 1];
+        const uint32_t lo = rfl(M.soff[b]), hi = rfl(M.soff[b + 1]);
         for (uint32_t t = lo; t < hi; ++t) {
-            const uint32_t nx = M.slist[t];
+            const uint32_t nx = rfl(M.slist[t]);
             uint32_t old = 0;
             if (lane == 0) old = M.pend[nx]--;
             old = rfl(old);
@@ -210,7 +210,7 @@ __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint
     if (lane == 0) left = M.grem[g]--;
     left = rfl(left);
     if (left == 1u) {
-        const uint32_t lo = M.gloff[g], hi = M.gloff[g + 1];
+        const uint32_t lo = rfl(M.gloff[g]), hi = rfl(M.gloff[g + 1]);
         for (uint32_t t0 = lo; t0 < hi; t0 += kWave) {
             const uint32_t t = t0 + lane;
             uint32_t h = 0;
@@ -224,8 +224,9 @@ __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint
                 const int l = ffs64(zm);
                 zm &= zm - 1;
                 const uint32_t hh = rdl(h, l);
-                for (uint32_t u = M.hdoff[hh]; u < M.hdoff[hh + 1]; ++u)
-                    ok &= insert_ready(R, M, M.hd[u], hh, -1, -1, moved);
+                const uint32_t ulo = rfl(M.hdoff[hh]), uhi = rfl(M.hdoff[hh + 1]);
+                for (uint32_t u = ulo; u < uhi; ++u)
+                    ok &= insert_ready(R, M, rfl(M.hd[u]), hh, -1, -1, moved);
             }
         }
     }
@@ -272,7 +273,7 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
             entry_of(M.mv[b], c, e, n);
             M.scratch[at] = make_uint4(c, e, n, (b << 10) | g);
         }
-        n0 += (uint32_t)__shfl((int)inc, kWave - 1, kWave);
+        n0 += rfl((uint32_t)__shfl((int)inc, kWave - 1, kWave));
     }
     wave_sync();
     bool err = n0 > (uint32_t)(kWave * S);
@@ -379,7 +380,7 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
                     any |= ballot(ok) != 0ull;
                     tv = ok && t < tv ? t : tv;
                 }
-                if (any) ts = (uint32_t)wave_min_i((int)tv);
+                if (any) ts = rfl((uint32_t)wave_min_i((int)tv));   // uniform: keeps the leader scalar
             }
             for (uint32_t j = lane; j < ts; j += kWave) {
                 if (out + j < I.step_cap) I.steps[out + j] = lc + j * delta;

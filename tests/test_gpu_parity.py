@@ -115,7 +115,7 @@ def test_adversarial_solve_and_batch(name, shape, fn):
             rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF)
             same_batch(gb, rb, f"{name} flags={flags:#x}")
             if not big:
-                check_batches(shape, occ, g["moves"], g["final"], gb["batch_off"], gb["steps"], flags)
+                check_batches(shape, occ, g["moves"], g["final"], gb["batch_off"], gb["steps"], flags & 0xFF)
 
 
 @pytest.mark.parametrize("seed", range(24))
