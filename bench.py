@@ -287,7 +287,7 @@ def main():
         if good and r["status"] == 0:
             good = np.array_equal(g["moves"], r["moves"]) and np.array_equal(g["group_off"], r["group_off"])
             gb = mb.host_batch(i, binf, st, bo)
-            rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=args.flags)
+            rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=args.flags & 0xFF)
             good = good and np.array_equal(gb["batch_off"], rb["batch_off"]) and np.array_equal(gb["steps"], rb["steps"])
         exact += int(good)
 

@@ -113,9 +113,10 @@ size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step
  *                                 move off the grid, a move of length 0 or a malformed group_off).
  *   move_cap   [in]  capacity of `moves` (>= sinfo->n_moves), used to size the workspace.
  *   flags      [in]  bits 0..7: RR_LAMBDA_*; bits 8..15: LDS budget in KiB (1..255) for the loop
- *                    data of one instance, 0 = the library's default; bit 16: RR_BATCH_GENERIC.
- *                    Bits 8..16 are tuning and testing knobs: results do not depend on them.
- *                    Bits 17..31 must be 0.
+ *                    data of one instance, 0 = the library's default; bit 16: RR_BATCH_GENERIC;
+ *                    bits 24..31: LDS budget in KiB for the dependency-graph build of one
+ *                    instance, 0 = the library's default.  Bits 8..16 and 24..31 are tuning and
+ *                    testing knobs: results do not depend on them.  Bits 17..23 must be 0.
  *                    At most 2^20 - 1 moves in at most 1024 groups (always true for rr_solve
  *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.
  *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).

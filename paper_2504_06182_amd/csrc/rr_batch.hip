@@ -96,8 +96,8 @@ __global__ __launch_bounds__(fast::kGT) void k_graph_many(const rr_desc *__restr
 
 // ---- loop kernels
 
-template <int S>
-__device__ __forceinline__ void loop_entry(const fast::Inst &I, uint32_t lds_bytes, uint32_t flags)
+template <int S, uint32_t F>
+__device__ __forceinline__ void loop_entry(const fast::Inst &I, uint32_t lds_bytes)
 {
     const fast::Layout L = fast::layout(I.W, I.H, I.move_cap, I.step_cap);
     uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
@@ -106,26 +106,26 @@ __device__ __forceinline__ void loop_entry(const fast::Inst &I, uint32_t lds_byt
         if (lane_id() == 0) hdr[fast::H_STATE] = fast::ST_GENERIC;
         return;
     }
-    fast::loop_fast<S>(I, dyn_lds, lds_bytes, flags & 0xFFu);
+    fast::loop_fast<S, F>(I, dyn_lds, lds_bytes);
 }
 
-template <int S>
-__global__ __launch_bounds__(kWave) void k_loop_one(fast::Inst I, uint32_t lds_bytes, uint32_t flags)
+// S register slots, F the local constraint (a compile-time constant: one kernel per constraint)
+template <int S, uint32_t F>
+__global__ __launch_bounds__(kWave) void k_loop_one(fast::Inst I, uint32_t lds_bytes)
 {
-    loop_entry<S>(I, lds_bytes, flags);
+    loop_entry<S, F>(I, lds_bytes);
 }
 
-template <int S>
+template <int S, uint32_t F>
 __global__ __launch_bounds__(kWave) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                      const rr_move *mv, const uint32_t *ga,
                                                      const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
-                                                     rr_batch_info *binfos, uint8_t *ws, uint32_t lds_bytes,
-                                                     uint32_t flags)
+                                                     rr_batch_info *binfos, uint8_t *ws, uint32_t lds_bytes)
 {
     const uint32_t i = blockIdx.x;
     const rr_desc d = desc[i];
     if (!desc_usable(d, maxw, maxh)) return;
-    loop_entry<S>(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), lds_bytes, flags);
+    loop_entry<S, F>(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), lds_bytes);
 }
 
 // ---- general path
@@ -259,9 +259,15 @@ struct Plan {
     uint32_t graph_lds, loop_lds, gen_lds;
 };
 
-// LDS budgets: the graph kernel takes the per-trap arrays of grids up to 64 x 64 (about 62 KiB for
-// a 64 x 64 shot of ~21k trap visits); the loop kernel takes the loop data of one instance
-// (flags bits 8..15 override its budget in KiB); the general path its 16-bit loop state.
+// LDS budgets.  Graph kernel: 64 KiB for grids up to 64 x 64, two workgroups per CU (a 64 x 64
+// shot of ~21k trap visits needs about 62 KiB; larger ones build in the workspace; measured:
+// 3.6 ms with 64 KiB against 5.6 ms with 96 KiB and 8.3 ms all in the workspace); flags bits
+// 24..31 override it in KiB (0 = default).  Loop
+// kernel: for many-instance launches the loop data stays in the workspace by default -- the
+// kernel is latency-bound, and leaving LDS free lets every SIMD hold as many waves as its
+// registers allow (measured on the 8192-shot 64 x 64 workload: 10.2 ms with 1 KiB per wave
+// against 21.5 ms with 24 KiB); a single instance keeps its data in LDS.  Flags bits 8..15
+// override the loop budget in KiB.  General path: its 16-bit loop state.
 static Plan make_plan(uint32_t flags, uint32_t max_w, uint32_t max_h, bool single)
 {
     const uint32_t side = max_w > max_h ? max_w : max_h;
@@ -269,14 +275,16 @@ static Plan make_plan(uint32_t flags, uint32_t max_w, uint32_t max_h, bool singl
     const uint32_t gen_static = (uint32_t)sizeof(gen::BatchLds);
     Plan P;
     P.S = loop_slots(side);
-    P.graph_lds = side <= 64 ? 96u * 1024u : 0u;
-    if (single) P.graph_lds = 120u * 1024u;
+    const uint32_t gkib = (flags >> 24) & 0xFFu;
+    if (gkib) P.graph_lds = gkib * 1024u;
+    else P.graph_lds = single ? 120u * 1024u : (side <= 64 ? 64u * 1024u : 0u);
     if (P.graph_lds + sizeof(fast::GraphShared) > lim) P.graph_lds = lim - (uint32_t)sizeof(fast::GraphShared);
     uint32_t kib = (flags >> 8) & 0xFFu;
-    if (kib == 0) kib = single ? 64u : (side <= 64 ? 24u : (side <= 128 ? 64u : 0u));
+    if (kib == 0) kib = single ? 64u : 1u;
     P.loop_lds = kib * 1024u;
     if (P.loop_lds > lim) P.loop_lds = lim;
-    P.gen_lds = kib > 56u ? 56u * 1024u : kib * 1024u;
+    const uint32_t gkb = kib < 24u ? 24u : kib;
+    P.gen_lds = gkb > 56u ? 56u * 1024u : gkb * 1024u;
     if (P.gen_lds + gen_static > lim) P.gen_lds = lim - gen_static;
     return P;
 }
@@ -309,7 +317,7 @@ extern "C" rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const 
           shape.y1 <= shape.h))
         return RR_E_INVAL;
     if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
-    if ((flags & 0xFFu) > RR_LAMBDA_NONE || (flags >> 17) != 0) return RR_E_INVAL;
+    if ((flags & 0xFFu) > RR_LAMBDA_NONE || ((flags >> 17) & 0x7Fu) != 0) return RR_E_INVAL;
     if (!group_off || !sinfo || !batch_off || !binfo || (move_cap > 0 && !moves) || (step_cap > 0 && !steps))
         return RR_E_INVAL;
     if (((uintptr_t)moves & 7u) != 0) return RR_E_INVAL;
@@ -323,11 +331,20 @@ extern "C" rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const 
     const Plan P = make_plan(flags, shape.w, shape.h, true);
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_graph_one, dim3(1), dim3(fast::kGT), P.graph_lds, st, I, P.graph_lds, flags);
-    switch (P.S) {
-    case 3: hipLaunchKernelGGL(k_loop_one<3>, dim3(1), dim3(kWave), P.loop_lds, st, I, P.loop_lds, flags); break;
-    case 5: hipLaunchKernelGGL(k_loop_one<5>, dim3(1), dim3(kWave), P.loop_lds, st, I, P.loop_lds, flags); break;
-    default: hipLaunchKernelGGL(k_loop_one<8>, dim3(1), dim3(kWave), P.loop_lds, st, I, P.loop_lds, flags); break;
+#define RR_LOOP_ONE(SS, FF) hipLaunchKernelGGL((k_loop_one<SS, FF>), dim3(1), dim3(kWave), P.loop_lds, st, I, P.loop_lds)
+#define RR_LOOP_ONE_F(SS)                                                                                          \
+    switch (flags & 0xFFu) {                                                                                       \
+    case RR_LAMBDA_LINE_OR_COL: RR_LOOP_ONE(SS, RR_LAMBDA_LINE_OR_COL); break;                                     \
+    case RR_LAMBDA_ALONG: RR_LOOP_ONE(SS, RR_LAMBDA_ALONG); break;                                                 \
+    default: RR_LOOP_ONE(SS, RR_LAMBDA_NONE); break;                                                               \
     }
+    switch (P.S) {
+    case 3: RR_LOOP_ONE_F(3); break;
+    case 5: RR_LOOP_ONE_F(5); break;
+    default: RR_LOOP_ONE_F(8); break;
+    }
+#undef RR_LOOP_ONE_F
+#undef RR_LOOP_ONE
     hipLaunchKernelGGL(k_generic_one, dim3(1), dim3(kWave), P.gen_lds, st, I, P.gen_lds, flags);
     return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
 }
@@ -343,7 +360,7 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     if (n == 0) return RR_OK;
     if (!desc || !move_arena || !group_arena || !sinfos || !batch_arena || !step_arena || !binfos || !workspace)
         return RR_E_INVAL;
-    if ((flags & 0xFFu) > RR_LAMBDA_NONE || (flags >> 17) != 0 || max_w < 1 || max_h < 1) return RR_E_INVAL;
+    if ((flags & 0xFFu) > RR_LAMBDA_NONE || ((flags >> 17) & 0x7Fu) != 0 || max_w < 1 || max_h < 1) return RR_E_INVAL;
     if (max_w > RR_MAX_SIDE || max_h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
     if (((uintptr_t)move_arena & 7u) != 0) return RR_E_INVAL;
     const Plan P = make_plan(flags, max_w, max_h, false);
@@ -352,14 +369,21 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     hipLaunchKernelGGL(k_graph_many, dim3(n), dim3(fast::kGT), P.graph_lds, st, desc, (int)max_w, (int)max_h,
                        move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, P.graph_lds, flags);
     if (graph_done_event && hipEventRecord((hipEvent_t)graph_done_event, st) != hipSuccess) return RR_E_DEVICE;
-#define RR_LOOP_MANY(SS)                                                                                           \
-    hipLaunchKernelGGL(k_loop_many<SS>, dim3(n), dim3(kWave), P.loop_lds, st, desc, (int)max_w, (int)max_h,       \
-                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, P.loop_lds, flags)
-    switch (P.S) {
-    case 3: RR_LOOP_MANY(3); break;
-    case 5: RR_LOOP_MANY(5); break;
-    default: RR_LOOP_MANY(8); break;
+#define RR_LOOP_MANY(SS, FF)                                                                                       \
+    hipLaunchKernelGGL((k_loop_many<SS, FF>), dim3(n), dim3(kWave), P.loop_lds, st, desc, (int)max_w, (int)max_h,  \
+                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, P.loop_lds)
+#define RR_LOOP_MANY_F(SS)                                                                                         \
+    switch (flags & 0xFFu) {                                                                                       \
+    case RR_LAMBDA_LINE_OR_COL: RR_LOOP_MANY(SS, RR_LAMBDA_LINE_OR_COL); break;                                    \
+    case RR_LAMBDA_ALONG: RR_LOOP_MANY(SS, RR_LAMBDA_ALONG); break;                                                \
+    default: RR_LOOP_MANY(SS, RR_LAMBDA_NONE); break;                                                              \
     }
+    switch (P.S) {
+    case 3: RR_LOOP_MANY_F(3); break;
+    case 5: RR_LOOP_MANY_F(5); break;
+    default: RR_LOOP_MANY_F(8); break;
+    }
+#undef RR_LOOP_MANY_F
 #undef RR_LOOP_MANY
     if (loop_done_event && hipEventRecord((hipEvent_t)loop_done_event, st) != hipSuccess) return RR_E_DEVICE;
     hipLaunchKernelGGL(k_generic_many, dim3(n), dim3(kWave), P.gen_lds, st, desc, (int)max_w, (int)max_h, move_arena,

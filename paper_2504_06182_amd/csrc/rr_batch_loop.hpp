@@ -19,10 +19,15 @@
 // the line, and output positions are prefix popcounts, so the steps of a batch are written in
 // index order with one store.
 //
-// Leader runs.  When nothing ready is compatible with the leader, the leader steps alone; the
-// ready set cannot change until some move moves, so the next batches are the leader's steps
-// alone until it ends its leg or reaches the line of a waiting compatible move.  That count
-// is found with one wave-wide minimum and the batches are written in one go.
+// Convoys.  After a batch, nothing changes until some member ends its leg or a waiting move
+// comes onto the line that sweeps with the leader (its column on a horizontal leg, its row on a
+// vertical one), so the same members keep stepping together: the batch repeats.  The repeat
+// count is the smaller of the members' remaining leg lengths and the distance to the first
+// waiting move on the sweeping line that would change the batch (any one when the batch is the
+// leader alone or runs across the motion, one ordered before the first other member when it
+// runs along it), one DPP wave minimum; the repeats are written in one go.  On the 64x64
+// workload this turns ~10k batches into ~1.9k trips of the loop.  While the ready set fits one
+// slot (the common case) the trip runs on slot 0 alone.
 //
 // Completions.  A finished move leaves a hole.  Its release code (LDS) gives its successor:
 // the common case -- one successor waiting on nothing else -- takes the finished move's place
@@ -140,62 +145,70 @@ __device__ __forceinline__ bool merge_insert(Ready<S> &R, uint4 *scr, uint32_t c
 
 // Add ready move b (group g).  (ps, pl) is the slot/lane of the move that released it (a hole
 // now) or ps < 0.  Returns false on overflow (cannot happen when the ready-set bound holds).
-template <int S>
+// NS: slots that may hold entries (slots NS.. are empty when NS < S; checked here, so that an
+// earlier insertion of the same release that went beyond slot NS-1 is seen).
+template <int NS, int S>
 __device__ __forceinline__ bool insert_ready(Ready<S> &R, const LoopMem &M, uint32_t b, uint32_t g, int ps, int pl,
                                              bool &moved)
 {
-    const int lane = lane_id();
+    if (NS < S) {
+        uint64_t high = 0;
+#pragma unroll
+        for (int s = NS; s < S; ++s) high |= R.vm[s];
+        if (high) return insert_ready<S, S>(R, M, b, g, ps, pl, moved);
+    }
     uint32_t c0, e0, n0;
     entry_of(rfl(M.mv[b]), c0, e0, n0);
     const uint32_t k0 = (b << 10) | g;
-    int lo = -1, hi = kWave * S;
+    int lo = -1, hi = kWave * NS;               // with NS < S, position 64*NS starts the empty slots
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
+    for (int s = 0; s < NS; ++s) {
         const uint64_t v = R.vm[s];
         if (v) {
             const uint64_t lt = ballot(R.k[s] < k0) & v, gt = v & ~lt;
             if (lt) lo = s * kWave + fls64(lt);
-            if (gt && hi == kWave * S) hi = s * kWave + ffs64(gt);
+            if (gt && hi == kWave * NS) hi = s * kWave + ffs64(gt);
         }
     }
     int pos = -1;
-    if (ps >= 0) {
+    if (ps >= 0 && ps < NS) {
         const int pp = ps * kWave + pl;
         uint64_t hv = 0;
 #pragma unroll
-        for (int s = 0; s < S; ++s)
+        for (int s = 0; s < NS; ++s)
             if (s == ps) hv = R.vm[s];
         if (lo < pp && pp < hi && !((hv >> pl) & 1ull)) pos = pp;
     }
     if (pos < 0 && hi - lo > 1) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
+        for (int s = 0; s < NS; ++s) {
             if (pos >= 0) continue;
             const int a = lo + 1 - s * kWave, z = hi - 1 - s * kWave;
             const uint64_t holes = ~R.vm[s] & range_mask(a, z);
             if (holes) pos = s * kWave + ffs64(holes);
         }
     }
+    if (NS < S && pos < 0 && hi == kWave * NS) pos = kWave * NS;   // after every entry: first empty slot
     if (pos >= 0) {
         put_entry(R, pos / kWave, pos % kWave, c0, e0, n0, k0);
-        (void)lane;
         return true;
     }
     moved = true;
     return merge_insert(R, M.scratch, c0, e0, n0, k0);
 }
 
-// Successors of finished move b (group g) and, when b was its group's last move, the groups
-// waiting on that group.
-template <int S>
-__device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint32_t b, uint32_t g, int ps, int pl, bool &moved)
+// Successors of finished move b (group g) -- unless the caller placed it already -- and, when b
+// was its group's last move, the groups waiting on that group.
+template <int NS, int S>
+__device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint32_t b, uint32_t g, int ps, int pl, bool &moved,
+                                             bool successors)
 {
     const int lane = lane_id();
     bool ok = true;
-    const uint32_t code = rfl(M.nx[b]);
+    const uint32_t code = successors ? rfl(M.nx[b]) : 0u;
     const uint32_t kind = code >> 14;
     if (kind == kRelNext) {
-        ok &= insert_ready(R, M, b + (code & kMaxDelta), g, ps, pl, moved);
+        ok &= insert_ready<NS, S>(R, M, b + (code & kMaxDelta), g, ps, pl, moved);
     } else if (kind == kRelList) {
         const uint32_t lo = rfl(M.soff[b]), hi = rfl(M.soff[b + 1]);
         for (uint32_t t = lo; t < hi; ++t) {
@@ -203,7 +216,7 @@ __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint
             uint32_t old = 0;
             if (lane == 0) old = M.pend[nx]--;
             old = rfl(old);
-            if (old == 1u) ok &= insert_ready(R, M, nx, g, ps, pl, moved);
+            if (old == 1u) ok &= insert_ready<NS, S>(R, M, nx, g, ps, pl, moved);
         }
     }
     uint32_t left = 0;
@@ -226,17 +239,13 @@ __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint
                 const uint32_t hh = rdl(h, l);
                 const uint32_t ulo = rfl(M.hdoff[hh]), uhi = rfl(M.hdoff[hh + 1]);
                 for (uint32_t u = ulo; u < uhi; ++u)
-                    ok &= insert_ready(R, M, rfl(M.hd[u]), hh, -1, -1, moved);
+                    ok &= insert_ready<NS, S>(R, M, rfl(M.hd[u]), hh, -1, -1, moved);
             }
         }
     }
     return ok;
 }
 
-struct LoopOut {
-    uint32_t *steps, *boff;
-    uint32_t step_cap, batch_cap;
-};
 
 template <int S>
 __device__ __forceinline__ void find_leader(const Ready<S> &R, int &ls, int &ll, uint32_t &lc, uint32_t &le,
@@ -252,10 +261,285 @@ __device__ __forceinline__ void find_leader(const Ready<S> &R, int &ls, int &ll,
         if (s == ls) { lc = rdl(R.c[s], ll); le = rdl(R.e[s], ll); ln = rdl(R.n[s], ll); lk = rdl(R.k[s], ll); }
 }
 
-// Alg. 3 iterations of one instance over its loop data M.
+// Minimum of one value per lane, uniform: DPP prefix minimum inside each 16-lane row, row
+// broadcasts to lane 63, then a read of lane 63 (no LDS traffic).
+__device__ __forceinline__ uint32_t wave_min_dpp(uint32_t v)
+{
+    auto m = [](uint32_t a, uint32_t b) { return a < b ? a : b; };
+    v = m(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = m(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = m(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = m(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = m(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = m(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return rdl(v, kWave - 1);
+}
+
+// position of a step code along the axis of a leg (column for a horizontal leg, row else)
+__device__ __forceinline__ uint32_t axis_pos(uint32_t c, bool horiz) { return horiz ? (c >> 15) & 0x1FFu : c & 0x1FFu; }
+
+// Scalar state of the loop (kept in SGPRs).
+struct LoopCtx {
+    uint32_t alive, out, nb, T;
+    int ls, ll;                 // leader position
+    uint32_t lc, le, ln, lk;    // leader entry
+    bool err;
+};
+
+// Compact the ready set into the lowest positions through LDS scratch (index order kept).
 template <int S>
-__device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32_t K, uint32_t G, uint32_t T,
-                                         uint32_t flags)
+__device__ __forceinline__ void compact(Ready<S> &R, uint4 *scr)
+{
+    const int lane = lane_id();
+    uint32_t base = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint64_t v = R.vm[s];
+        if ((v >> lane) & 1ull) scr[base + mbcnt(v)] = make_uint4(R.c[s], R.e[s], R.n[s], R.k[s]);
+        base += (uint32_t)popc(v);
+    }
+    wave_sync();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const uint32_t p = (uint32_t)(s * kWave + lane);
+        const bool v = p < base;
+        const uint4 q = v ? scr[p] : make_uint4(kInv, kInv, kInv, kInv);
+        R.c[s] = q.x; R.e[s] = q.y; R.n[s] = q.z; R.k[s] = q.w;
+        R.vm[s] = ballot(v);
+    }
+    wave_sync();
+}
+
+// One trip of the loop over the first NS slots (the others are empty when NS < S): a batch --
+// the leader alone, or the leader and the ready moves stepping its way on its row or column --
+// then the same batch repeated while it stays the batch Alg. 3 would pick (the convoy), then
+// the legs that ended turn or finish and the finished moves release their successors.
+template <int NS, int S, uint32_t flags>
+__device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, const LoopMem &M)
+{
+    const int lane = lane_id();
+    const uint32_t d1 = X.lc >> 30;
+    const uint32_t delta = step_delta(d1);
+    const bool horiz = d1 < 2u;
+    const uint64_t lbit = 1ull << X.ll;
+    uint64_t acc[NS];
+    bool along = false;
+    uint32_t amin = kInv;                       // key of the first member after the leader
+    if (flags == RR_LAMBDA_NONE) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) acc[s] = R.vm[s];
+    } else {
+        const uint32_t ky = X.lc & kMaskY, kx = X.lc & kMaskX;
+        const bool use_row = flags != RR_LAMBDA_ALONG || horiz;
+        const bool use_col = flags != RR_LAMBDA_ALONG || !horiz;
+        bool found = false, row = false;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (found || !R.vm[s]) continue;
+            uint64_t mr = use_row ? ballot((R.c[s] & kMaskY) == ky) : 0ull;
+            uint64_t mc = use_col ? ballot((R.c[s] & kMaskX) == kx) : 0ull;
+            if (s == X.ls) { mr &= ~lbit; mc &= ~lbit; }
+            if (mr | mc) {
+                found = true;
+                row = (mr >> ffs64(mr | mc)) & 1ull;
+            }
+        }
+        if (found) {
+            along = row == horiz;
+            const uint32_t km = row ? kMaskY : kMaskX, kv = row ? ky : kx;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                acc[s] = R.vm[s] ? ballot((R.c[s] & km) == kv) : 0ull;
+                if (along && amin == kInv) {
+                    const uint64_t m = s == X.ls ? acc[s] & ~lbit : acc[s];
+                    if (m) amin = rdl(R.k[s], ffs64(m));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) acc[s] = 0;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+            if (s == X.ls) acc[s] |= lbit;
+    }
+
+    // ---- the batch: members store their step codes in index order and step
+    uint32_t base = 0;
+    uint64_t arr[NS];
+    bool any_arr = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        arr[s] = 0;
+        const uint64_t a = acc[s];
+        if (!a) continue;
+        const bool me = (a >> lane) & 1ull;
+        const uint32_t at = X.out + base + mbcnt(a);
+        if (me) {
+            if (at < I.step_cap) I.steps[at] = R.c[s];
+            R.c[s] += flags == RR_LAMBDA_NONE ? step_delta(R.c[s] >> 30) : delta;
+        }
+        arr[s] = ballot(me && R.c[s] == R.e[s]);
+        any_arr |= arr[s] != 0ull;
+        base += (uint32_t)popc(a);
+    }
+    X.out += base;
+    ++X.nb;
+    if (lane == 0 && X.nb <= I.batch_cap) I.boff[X.nb] = X.out;
+    X.lc += delta;
+
+    // ---- the convoy: the same members step again until one ends its leg, or until a waiting
+    //      move on the line that sweeps with the leader would change the batch
+    if (!any_arr) {
+        uint32_t tv = 1u << 20;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const uint64_t a = acc[s];
+            if (!a) continue;
+            if ((a >> lane) & 1ull) {
+                const bool h = (R.c[s] >> 30) < 2u;
+                const uint32_t pc = axis_pos(R.c[s], h), pe = axis_pos(R.e[s], h);
+                const uint32_t rem = pc > pe ? pc - pe : pe - pc;
+                tv = rem < tv ? rem : tv;
+            }
+        }
+        if (flags == RR_LAMBDA_LINE_OR_COL) {
+            const uint32_t p1 = axis_pos(X.lc, horiz);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint64_t waiting = R.vm[s] & ~acc[s];
+                if (!waiting) continue;
+                const uint32_t c = R.c[s];
+                const uint32_t p = axis_pos(c, horiz);
+                const uint32_t t = (d1 & 1u) ? p1 - p : p - p1;          // wraps when behind
+                const bool blk = ((waiting >> lane) & 1ull) && (c >> 30) == d1 && (!along || R.k[s] < amin);
+                tv = blk && t < tv ? t : tv;
+            }
+        }
+        const uint32_t ts = wave_min_dpp(tv);
+        if (ts > 0) {
+            uint32_t rank = 0;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                uint64_t m = acc[s];
+                while (m) {
+                    const int l = ffs64(m);
+                    m &= m - 1;
+                    const uint32_t cm = rdl(R.c[s], l);
+                    const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(cm >> 30) : delta;
+                    for (uint32_t j = lane; j < ts; j += kWave) {
+                        const uint32_t at = X.out + j * base + rank;
+                        if (at < I.step_cap) I.steps[at] = cm + j * dl;
+                    }
+                    ++rank;
+                }
+            }
+            for (uint32_t j = lane; j < ts; j += kWave)
+                if (X.nb + 1 + j <= I.batch_cap) I.boff[X.nb + 1 + j] = X.out + (j + 1) * base;
+            X.out += ts * base;
+            X.nb += ts;
+            X.lc += ts * delta;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint64_t a = acc[s];
+                if (!a) continue;
+                const bool me = (a >> lane) & 1ull;
+                if (me) R.c[s] += ts * (flags == RR_LAMBDA_NONE ? step_delta(R.c[s] >> 30) : delta);
+                arr[s] = ballot(me && R.c[s] == R.e[s]);
+                any_arr |= arr[s] != 0ull;
+            }
+        }
+    }
+    if (!any_arr) return;
+
+    // ---- legs ended: turn onto the vertical leg, or finish
+    uint64_t done[NS];
+    uint32_t ndone = 0;
+    bool ldone = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        done[s] = 0;
+        if (!arr[s]) continue;
+        const bool me = (arr[s] >> lane) & 1ull;
+        const bool turn = me && R.n[s] != kInv;
+        done[s] = ballot(me && !turn);
+        if (turn) {
+            R.c[s] = (R.c[s] & 0x3FFFFFFFu) | (R.n[s] & 0xC0000000u);
+            R.e[s] = R.n[s];
+            R.n[s] = kInv;
+        }
+        if (s == X.ls && ((arr[s] >> X.ll) & 1ull)) {
+            if ((done[s] >> X.ll) & 1ull) ldone = true;
+            else { X.lc = (X.lc & 0x3FFFFFFFu) | (X.ln & 0xC0000000u); X.le = X.ln; X.ln = kInv; }
+        }
+        ndone += (uint32_t)popc(done[s]);
+    }
+    if (ndone == 0) return;
+
+    // ---- finished moves release what waited on them.  The common release -- the next move
+    //      index, waiting on nothing else -- takes the finished move's position (no index lies
+    //      between them); the others leave a hole and go through the general insertion.
+    uint32_t dk[NS];
+    uint64_t slow[NS];
+    bool any_slow = false;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        slow[s] = 0;
+        if (!done[s]) continue;
+        dk[s] = R.k[s];
+        uint64_t m = done[s];
+        while (m) {
+            const int l = ffs64(m);
+            m &= m - 1;
+            const uint32_t kk = rdl(dk[s], l);
+            const uint32_t b = kk >> 10;
+            if (rfl(M.nx[b]) == ((kRelNext << 14) | 1u)) {
+                uint32_t c0, e0, n0;
+                entry_of(rfl(M.mv[b + 1]), c0, e0, n0);
+                const uint32_t k0 = kk + (1u << 10);
+                if (lane == l) { R.c[s] = c0; R.e[s] = e0; R.n[s] = n0; R.k[s] = k0; }
+                if (s == X.ls && l == X.ll) { X.lc = c0; X.le = e0; X.ln = n0; X.lk = k0; ldone = false; }
+            } else {
+                slow[s] |= 1ull << l;
+            }
+        }
+        if (slow[s]) {
+            if ((slow[s] >> lane) & 1ull) { R.c[s] = kInv; R.k[s] = kInv; }
+            R.vm[s] &= ~slow[s];
+            any_slow = true;
+        }
+    }
+    X.alive -= ndone;
+    bool moved = false, ok = true;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        uint64_t m = done[s];
+        while (m) {
+            const int l = ffs64(m);
+            m &= m - 1;
+            const uint32_t kk = rdl(dk[s], l);
+            ok &= release_move<NS, S>(R, M, kk >> 10, kk & 0x3FFu, s, l, moved, ((slow[s] >> l) & 1ull) != 0);
+        }
+    }
+    (void)any_slow;
+    if (!ok) { X.err = true; return; }
+    // keep the set in slot 0 while it fits there, so that trips stay on the one-slot path
+    if (S > 1) {
+        uint32_t total = 0;
+        uint64_t high = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            total += (uint32_t)popc(R.vm[s]);
+            if (s > 0) high |= R.vm[s];
+        }
+        if (high && total <= (uint32_t)kWave) { compact(R, M.scratch); moved = true; }
+    }
+    if (ldone || moved) find_leader(R, X.ls, X.ll, X.lc, X.le, X.ln, X.lk);
+}
+
+// Alg. 3 iterations of one instance over its loop data M.
+template <int S, uint32_t flags>
+__device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32_t K, uint32_t G, uint32_t T)
 {
     const int lane = lane_id();
     // ---- initial ready set: head moves of the groups that wait on nothing, in index order
@@ -276,190 +560,45 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
         n0 += rfl((uint32_t)__shfl((int)inc, kWave - 1, kWave));
     }
     wave_sync();
-    bool err = n0 > (uint32_t)(kWave * S);
+    LoopCtx X;
+    X.err = n0 > (uint32_t)(kWave * S);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const uint32_t p = (uint32_t)(s * kWave + lane);
-        const bool v = !err && p < n0;
+        const bool v = !X.err && p < n0;
         const uint4 q = v ? M.scratch[p] : make_uint4(kInv, kInv, kInv, kInv);
         R.c[s] = q.x; R.e[s] = q.y; R.n[s] = q.z; R.k[s] = q.w;
         R.vm[s] = ballot(v);
     }
     wave_sync();
 
-    uint32_t alive = err ? 0u : K, out = 0, nb = 0;
+    X.alive = X.err ? 0u : K;
+    X.out = 0;
+    X.nb = 0;
+    X.T = T;
     if (lane == 0) I.boff[0] = 0;
-    int ls, ll;
-    uint32_t lc, le, ln, lk;
-    find_leader(R, ls, ll, lc, le, ln, lk);
+    find_leader(R, X.ls, X.ll, X.lc, X.le, X.ln, X.lk);
 
-    while (alive > 0) {
-        if (nb >= T || ls < 0) { err = true; break; }   // every batch holds a step: at most T
-        const uint32_t d1 = lc >> 30;
-        const uint32_t delta = step_delta(d1);
-        const uint64_t lbit = 1ull << ll;
-        uint64_t acc[S];
-        bool found = false;
-        if (flags == RR_LAMBDA_NONE) {
+    while (X.alive > 0) {
+        if (X.nb >= T || X.ls < 0) { X.err = true; break; }   // every batch holds a step: at most T
+        uint64_t high = 0;
 #pragma unroll
-            for (int s = 0; s < S; ++s) acc[s] = R.vm[s];
-            uint32_t others = 0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) others += (uint32_t)popc(R.vm[s]);
-            found = others > 1;
-        } else {
-            const uint32_t ky = lc & kMaskY, kx = lc & kMaskX;
-            const bool use_row = flags != RR_LAMBDA_ALONG || d1 < 2u;
-            const bool use_col = flags != RR_LAMBDA_ALONG || d1 >= 2u;
-            bool row = false;
-            uint64_t mr[S], mc[S];
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                mr[s] = 0;
-                mc[s] = 0;
-                if (R.vm[s]) {
-                    if (use_row) mr[s] = ballot((R.c[s] & kMaskY) == ky);
-                    if (use_col) mc[s] = ballot((R.c[s] & kMaskX) == kx);
-                    if (s == ls) { mr[s] &= ~lbit; mc[s] &= ~lbit; }
-                    if (!found && (mr[s] | mc[s])) {
-                        found = true;
-                        row = (mr[s] >> ffs64(mr[s] | mc[s])) & 1ull;
-                    }
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) acc[s] = row ? mr[s] : mc[s];
-            if (found) {
-#pragma unroll
-                for (int s = 0; s < S; ++s)
-                    if (s == ls) acc[s] |= lbit;
-            }
-        }
-
-        uint64_t arr[S];
-        if (found) {
-            // ---- one batch: the accepted moves step, in index order
-            uint32_t base = 0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                arr[s] = 0;
-                const uint64_t a = acc[s];
-                if (a) {
-                    const bool me = (a >> lane) & 1ull;
-                    const uint32_t at = out + base + mbcnt(a);
-                    if (me) {
-                        if (at < I.step_cap) I.steps[at] = R.c[s];
-                        // without a constraint the batch mixes directions; else all step the leader's way
-                        R.c[s] += flags == RR_LAMBDA_NONE ? step_delta(R.c[s] >> 30) : delta;
-                    }
-                    arr[s] = ballot(me && R.c[s] == R.e[s]);
-                    base += (uint32_t)popc(a);
-                }
-            }
-            out += base;
-            ++nb;
-            if (lane == 0 && nb <= I.batch_cap) I.boff[nb] = out;
-            lc += delta;
-        } else {
-            // ---- the leader steps alone: up to its leg end or the first waiting compatible move
-            const bool horiz = d1 < 2u;
-            const uint32_t p1 = horiz ? (lc >> 15) & 0x1FFu : lc & 0x1FFu;
-            const uint32_t pe = horiz ? (le >> 15) & 0x1FFu : le & 0x1FFu;
-            const uint32_t len = p1 > pe ? p1 - pe : pe - p1;
-            uint32_t ts = len;
-            if (flags == RR_LAMBDA_LINE_OR_COL && len > 1u) {
-                uint32_t tv = len;
-                bool any = false;
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    if (!R.vm[s]) continue;
-                    const uint32_t c = R.c[s];
-                    const uint32_t p = horiz ? (c >> 15) & 0x1FFu : c & 0x1FFu;
-                    const uint32_t t = (d1 & 1u) ? p1 - p : p - p1;     // wraps when behind
-                    const bool ok = (c >> 30) == d1 && t >= 1u && t < len;
-                    any |= ballot(ok) != 0ull;
-                    tv = ok && t < tv ? t : tv;
-                }
-                if (any) ts = rfl((uint32_t)wave_min_i((int)tv));   // uniform: keeps the leader scalar
-            }
-            for (uint32_t j = lane; j < ts; j += kWave) {
-                if (out + j < I.step_cap) I.steps[out + j] = lc + j * delta;
-                if (nb + 1 + j <= I.batch_cap) I.boff[nb + 1 + j] = out + j + 1;
-            }
-            out += ts;
-            nb += ts;
-            lc += ts * delta;
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                arr[s] = 0;
-                if (s == ls) {
-                    R.c[s] = wrl(lc, ll, R.c[s]);
-                    if (ts == len) arr[s] = lbit;
-                }
-            }
-        }
-
-        // ---- legs ended: turn onto the vertical leg, or finish
-        uint64_t done[S];
-        uint32_t ndone = 0;
-        bool ldone = false;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            done[s] = 0;
-            if (arr[s]) {
-                const bool me = (arr[s] >> lane) & 1ull;
-                const bool turn = me && R.n[s] != kInv;
-                done[s] = ballot(me && !turn);
-                if (turn) {
-                    R.c[s] = (R.c[s] & 0x3FFFFFFFu) | (R.n[s] & 0xC0000000u);
-                    R.e[s] = R.n[s];
-                    R.n[s] = kInv;
-                }
-                if (s == ls && ((arr[s] >> ll) & 1ull)) {
-                    if ((done[s] >> ll) & 1ull) ldone = true;
-                    else { lc = (lc & 0x3FFFFFFFu) | (ln & 0xC0000000u); le = ln; ln = kInv; }
-                }
-                ndone += (uint32_t)popc(done[s]);
-            }
-        }
-        if (ndone == 0) continue;
-
-        // ---- finished moves leave the ready set, then release what waited on them
-        uint32_t dk[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            dk[s] = R.k[s];
-            if (done[s]) {
-                if ((done[s] >> lane) & 1ull) { R.c[s] = kInv; R.k[s] = kInv; }
-                R.vm[s] &= ~done[s];
-            }
-        }
-        alive -= ndone;
-        bool moved = false, ok = true;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            uint64_t m = done[s];
-            while (m) {
-                const int l = ffs64(m);
-                m &= m - 1;
-                const uint32_t kk = rdl(dk[s], l);
-                ok &= release_move(R, M, kk >> 10, kk & 0x3FFu, s, l, moved);
-            }
-        }
-        if (!ok) { err = true; break; }
-        if (ldone || moved) find_leader(R, ls, ll, lc, le, ln, lk);
+        for (int s = 1; s < S; ++s) high |= R.vm[s];
+        if (!high) trip<1, S, flags>(R, X, I, M);
+        else trip<S, S, flags>(R, X, I, M);
+        if (X.err) break;
     }
 
     if (lane == 0) {
-        if (err) put_info(I.binfo, RR_E_INTERNAL, 0, 0, 0, 0);
-        else if (nb > I.batch_cap) put_info(I.binfo, RR_E_CAPACITY, 0, 0, nb, T);
-        else put_info(I.binfo, RR_OK, nb, out, nb, T);
+        if (X.err) put_info(I.binfo, RR_E_INTERNAL, 0, 0, 0, 0);
+        else if (X.nb > I.batch_cap) put_info(I.binfo, RR_E_CAPACITY, 0, 0, X.nb, T);
+        else put_info(I.binfo, RR_OK, X.nb, X.out, X.nb, T);
     }
 }
 
 // Run Alg. 3 on one instance whose graph is built (header state ST_FAST, bound <= 64*S).
-template <int S>
-__device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t lds_bytes, uint32_t flags)
+template <int S, uint32_t flags>
+__device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t lds_bytes)
 {
     const int lane = lane_id();
     const Layout L = layout(I.W, I.H, I.move_cap, I.step_cap);
@@ -499,7 +638,7 @@ __device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t 
         for (uint32_t i = lane; i < HN; i += kWave) hd[i] = ghd[i];
         M.mv = mv; M.nx = nx; M.grem = grem; M.gpend = gpend; M.gloff = go; M.hdoff = hdo; M.gl = gl; M.hd = hd;
         wave_sync();
-        loop_run<S>(I, M, K, G, T, flags);   // every LDS access of this copy compiles to ds_* operations
+        loop_run<S, flags>(I, M, K, G, T);   // every LDS access of this copy compiles to ds_* operations
     } else {
         // the workspace copy; the mutable counts go to the generic path's region, which is
         // unused on the fast path
@@ -512,7 +651,7 @@ __device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t 
         M.scratch = (uint4 *)(I.ws + L.scratch);
         M.mv = gmv; M.nx = gnx; M.grem = grem; M.gpend = gpend; M.gloff = ggo; M.hdoff = ghdo; M.gl = ggl; M.hd = ghd;
         wave_sync();
-        loop_run<S>(I, M, K, G, T, flags);
+        loop_run<S, flags>(I, M, K, G, T);
     }
 }
 

@@ -102,7 +102,15 @@ def find_leader(Rr):
             l = ffs(Rr.vm[s]); return s, l, Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l]
     return -1, 0, INV, INV, INV, INV
 
+def axis_pos(c, horiz):
+    return (c >> 15) & 0x1FF if horiz else c & 0x1FF
+
+
 def loop(Gd, S, flags):
+    """Alg. 3 over the graph Gd with 64*S register positions, as the loop kernel runs it: one batch
+    per trip (the leader alone, or the leader and the moves on its row or column that step its
+    way), then the same batch repeated -- the convoy -- until a member ends its leg or a waiting
+    move reaches the line that sweeps with the leader."""
     K, G = Gd['K'], Gd['G']
     T = sum(abs(((m >> 16) & 0xFF) - (m & 0xFF)) + abs((m >> 24) - ((m >> 8) & 0xFF)) for m in Gd['mv'])
     grem = [Gd['goff'][g + 1] - Gd['goff'][g] for g in range(G)]
@@ -117,69 +125,99 @@ def loop(Gd, S, flags):
     assert len(ents) <= 64 * S
     for p, q in enumerate(ents):
         s, l = divmod(p, 64); Rr.c[s][l], Rr.e[s][l], Rr.n[s][l], Rr.k[s][l] = q; Rr.vm[s] |= 1 << l
-    st = dict(inplace=0, hole=0, merge=0, moved=False, iters=0, bulk=0)
+    st = dict(inplace=0, hole=0, merge=0, moved=False, trips=0, repeats=0, bulk=0)
     alive = K; out = 0; nb = 0; steps = []; boff = [0]
     ls, ll, lc, le, ln, lk = find_leader(Rr)
     while alive > 0:
         if nb >= T or ls < 0: raise RuntimeError('err')
+        st['trips'] += 1
         d1 = lc >> 30; delta = delta_of(d1); lbit = 1 << ll
-        acc = [0] * S; found = False
+        horiz = d1 < 2
+        acc = [0] * S; found = False; along = False
         if flags == 2:
-            acc = list(Rr.vm); found = sum(popc(v) for v in Rr.vm) > 1
+            acc = list(Rr.vm); found = True
         else:
             ky, kx = lc & MY, lc & MX
             use_row = flags != 1 or d1 < 2; use_col = flags != 1 or d1 >= 2
-            row = False; mr = [0] * S; mc = [0] * S
+            row = False
             for s in range(S):
-                if Rr.vm[s]:
-                    if use_row: mr[s] = ballot([(Rr.c[s][l] & MY) == ky for l in range(64)])
-                    if use_col: mc[s] = ballot([(Rr.c[s][l] & MX) == kx for l in range(64)])
-                    if s == ls: mr[s] &= ~lbit; mc[s] &= ~lbit
-                    if not found and (mr[s] | mc[s]):
-                        found = True; row = bool((mr[s] >> ffs(mr[s] | mc[s])) & 1)
-            acc = [mr[s] if row else mc[s] for s in range(S)]
-            if found: acc[ls] |= lbit
-        arr = [0] * S
-        if found:
-            st['iters'] += 1
-            base = 0
+                if Rr.vm[s] and not found:
+                    mr = ballot([(Rr.c[s][l] & MY) == ky for l in range(64)]) if use_row else 0
+                    mc = ballot([(Rr.c[s][l] & MX) == kx for l in range(64)]) if use_col else 0
+                    if s == ls: mr &= ~lbit; mc &= ~lbit
+                    if mr | mc:
+                        found = True; row = bool((mr >> ffs(mr | mc)) & 1)
+            if found:
+                along = row == horiz
+                for s in range(S):
+                    if Rr.vm[s]:
+                        acc[s] = ballot([((Rr.c[s][l] & (MY if row else MX)) == (ky if row else kx)) for l in range(64)])
+            acc[ls] |= lbit
+        # first member after the leader (along batches): its key bounds the sweeping-line blockers
+        amin = None
+        if found and along:
+            for s in range(S):
+                m = acc[s] & ~(lbit if s == ls else 0)
+                if m and amin is None: amin = Rr.k[s][ffs(m)]
+        # ---- the batch: members step in index order
+        base = 0; arr = [0] * S
+        for s in range(S):
+            a = acc[s]
+            if a:
+                for l in range(64):
+                    if (a >> l) & 1:
+                        assert out + base + popc(a & ((1 << l) - 1)) == len(steps)
+                        steps.append(Rr.c[s][l])
+                        Rr.c[s][l] = (Rr.c[s][l] + (delta_of(Rr.c[s][l] >> 30) if flags == 2 else delta)) & M32
+                arr[s] = ballot([((a >> l) & 1) and Rr.c[s][l] == Rr.e[s][l] for l in range(64)])
+                base += popc(a)
+        out += base; nb += 1; boff.append(out); lc = (lc + delta) & M32
+        # ---- the convoy: repeats of the same batch
+        if not any(arr):
+            tv = [1 << 20] * 64
             for s in range(S):
                 a = acc[s]
                 if a:
-                    me = [(a >> l) & 1 for l in range(64)]
                     for l in range(64):
-                        if me[l]:
-                            at = out + base + popc(a & ((1 << l) - 1))
-                            assert at == len(steps); steps.append(Rr.c[s][l])
-                            Rr.c[s][l] = (Rr.c[s][l] + (delta_of(Rr.c[s][l] >> 30) if flags == 2 else delta)) & M32
-                    arr[s] = ballot([me[l] and Rr.c[s][l] == Rr.e[s][l] for l in range(64)])
-                    base += popc(a)
-            out += base; nb += 1; boff.append(out); lc = (lc + delta) & M32
-        else:
-            st['bulk'] += 1
-            horiz = d1 < 2
-            p1 = (lc >> 15) & 0x1FF if horiz else lc & 0x1FF
-            pe = (le >> 15) & 0x1FF if horiz else le & 0x1FF
-            ln_ = abs(p1 - pe); ts = ln_
-            if flags == 0 and ln_ > 1:
-                tv = [ln_] * 64; anyok = False
+                        if (a >> l) & 1:
+                            c, e = Rr.c[s][l], Rr.e[s][l]
+                            h = (c >> 30) < 2
+                            rem = abs(axis_pos(e, h) - axis_pos(c, h))
+                            tv[l] = min(tv[l], rem)
+            if flags == 0:
+                p1 = axis_pos(lc, horiz)                      # the leader's new position
                 for s in range(S):
-                    if not Rr.vm[s]: continue
-                    oks = []
-                    for l in range(64):
-                        c = Rr.c[s][l]
-                        p = (c >> 15) & 0x1FF if horiz else c & 0x1FF
-                        t = ((p1 - p) if (d1 & 1) else (p - p1)) & M32
-                        ok = (c >> 30) == d1 and 1 <= t < ln_
-                        oks.append(ok)
-                        if ok and t < tv[l]: tv[l] = t
-                    anyok |= ballot(oks) != 0
-                if anyok: ts = min(tv)
-            for j in range(ts):
-                steps.append((lc + j * delta) & M32); boff.append(out + j + 1)
-            out += ts; nb += ts; lc = (lc + ts * delta) & M32
-            Rr.c[ls][ll] = lc
-            if ts == ln_: arr[ls] = lbit
+                    if Rr.vm[s]:
+                        for l in range(64):
+                            if (Rr.vm[s] >> l) & 1 and not (acc[s] >> l) & 1:
+                                c = Rr.c[s][l]
+                                if (c >> 30) != d1: continue
+                                if along and Rr.k[s][l] > amin: continue
+                                # on the sweeping line: column for a horizontal leg, row for a vertical one
+                                p = axis_pos(c, horiz)
+                                t = ((p1 - p) if (d1 & 1) else (p - p1)) & M32
+                                if t < tv[l]: tv[l] = t
+            ts = min(tv)
+            if ts > 0:
+                st['repeats'] += ts; st['bulk'] += 1
+                for j in range(ts):
+                    for s in range(S):
+                        a = acc[s]
+                        for l in range(64):
+                            if (a >> l) & 1:
+                                dl = delta_of(Rr.c[s][l] >> 30) if flags == 2 else delta
+                                steps.append((Rr.c[s][l] + j * dl) & M32)
+                    boff.append(out + (j + 1) * base)
+                out += ts * base; nb += ts; lc = (lc + ts * delta) & M32
+                for s in range(S):
+                    a = acc[s]
+                    if a:
+                        for l in range(64):
+                            if (a >> l) & 1:
+                                dl = delta_of(Rr.c[s][l] >> 30) if flags == 2 else delta
+                                Rr.c[s][l] = (Rr.c[s][l] + ts * dl) & M32
+                        arr[s] = ballot([((a >> l) & 1) and Rr.c[s][l] == Rr.e[s][l] for l in range(64)])
+        # ---- legs ended: turn or finish
         done = [0] * S; ndone = 0; ldone = False
         for s in range(S):
             if arr[s]:
@@ -193,7 +231,9 @@ def loop(Gd, S, flags):
                     if (done[s] >> ll) & 1: ldone = True
                     else: lc = (lc & 0x3FFFFFFF) | (ln & 0xC0000000); le = ln; ln = INV
                 ndone += popc(done[s])
-        if ndone == 0: continue
+        if ndone == 0:
+            assert Rr.c[ls][ll] == lc and Rr.e[ls][ll] == le, 'leader cache'
+            continue
         dk = [list(Rr.k[s]) for s in range(S)]
         for s in range(S):
             if done[s]:
@@ -211,7 +251,6 @@ def loop(Gd, S, flags):
         if not ok: raise RuntimeError('overflow')
         if ldone or st['moved']: ls, ll, lc, le, ln, lk = find_leader(Rr)
         else:
-            # the cached leader must still match its lane
             assert Rr.c[ls][ll] == lc and Rr.e[ls][ll] == le and Rr.n[ls][ll] == ln, 'leader cache'
     return np.array(boff, np.uint32), np.array(steps, np.uint32), st
 

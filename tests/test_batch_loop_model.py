@@ -32,7 +32,7 @@ def test_model_matches_oracle(name, d):
         assert np.array_equal(pb, b["batch_off"]), (name, flags)
         assert np.array_equal(ps, b["steps"]), (name, flags)
         if flags == 0:
-            assert st["bulk"] > 0 and st["inplace"] > 0
+            assert st["repeats"] > 0 and st["inplace"] > 0
 
 
 def test_model_compaction_path():
