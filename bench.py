@@ -64,6 +64,31 @@ def cpu_baseline(seconds: float, max_workers: int):
                       f"{len(ranges)} single-threaded oracle processes; 1-core latency {calib * 1e3:.2f} ms/shot"}
 
 
+BATCH_SOURCES = ("rr_batch.hip", "rr_batch_graph.hpp", "rr_batch_loop.hpp", "rr_batch_generic.hpp", "rr_device.hpp")
+PROFILE = os.path.join(ROOT, "profiles", "k_loop_many_batch64.md")
+
+
+def measured_traffic():
+    """HBM bytes of one k_loop_many launch from the committed rocprofv3 PMC summary (FETCH_SIZE +
+    WRITE_SIZE scaled by a plain copy), or None when that summary was taken on other kernel
+    sources than the ones built now."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in BATCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_06182_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch k_loop_many<3,0> (\d+) sources_sha256 ([0-9a-f]+)", text)
+    if not m or m.group(2) != sha:
+        return None
+    return float(m.group(1))
+
+
 def mixed_step_bound(shape):
     """Pool-sizing estimate of one shot's step count (about 0.07 * side**3 for these loadings);
     the device planner reports exact totals and the pools grow once when the estimate is short."""
@@ -317,7 +342,7 @@ def main():
 
     value = n / (ms_per_step / 1e3)
     achieved = bytes_batch / (k_loop / 1e3) / 1e9
-    traffic = None if args.traffic_gb is None else args.traffic_gb * 1e9
+    traffic = measured_traffic() if args.traffic_gb is None else args.traffic_gb * 1e9
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -339,7 +364,7 @@ def main():
                        "batch_generic": round(k_generic, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic, "kernel": "k_loop_many<3>",
+                     "traffic": traffic, "kernel": "k_loop_many<3,0>",
                      "algorithmic_bytes_per_launch": bytes_batch},
         "solve_roofline": {"achieved": round(bytes_solve / (k_solve / 1e3) / 1e9, 2), "unit": "GB/s",
                            "algorithmic_bytes_per_launch": bytes_solve},
