@@ -7,8 +7,9 @@
 //   k_loop_*    one wave64 per instance: Alg. 3 with the ready set in registers
 //               (rr_batch_loop.hpp), for every instance the graph kernel passed on;
 //   k_generic_* one wave64 per instance: the general path (rr_batch_generic.hpp) for the
-//               instances outside the fast path's limits (more than 65535 moves, a ready set
-//               that could outgrow the registers, unusual graphs) -- every other wave exits.
+//               instances outside the fast path's limits (more than 65535 moves, unusual
+//               graphs, a ready set that outgrew the registers during the loop, which then
+//               hands the instance over) -- every other wave exits.
 // Each instance's status moves through a header word in its workspace, so the three launches
 // need no host round trip.  Results do not depend on which path ran.
 #include "rr_device.hpp"
@@ -102,11 +103,8 @@ __device__ __forceinline__ void loop_entry(const fast::Inst &I, uint32_t lds_byt
     const fast::Layout L = fast::layout(I.W, I.H, I.move_cap, I.step_cap);
     uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
     if (hdr[fast::H_STATE] != fast::ST_FAST) return;
-    if (hdr[fast::H_BOUND] > (uint32_t)(kWave * S)) {
-        if (lane_id() == 0) hdr[fast::H_STATE] = fast::ST_GENERIC;
-        return;
-    }
-    fast::loop_fast<S, F>(I, dyn_lds, lds_bytes);
+    // a ready set that outgrows the registers hands the instance to the general path
+    if (fast::loop_fast<S, F>(I, dyn_lds, lds_bytes) && lane_id() == 0) hdr[fast::H_STATE] = fast::ST_GENERIC;
 }
 
 // S register slots, F the local constraint (a compile-time constant: one kernel per constraint)

@@ -21,8 +21,9 @@
 // list), successor lists and wait counts for the general case, and per group its number of
 // group predecessors, the groups waiting on it and its head moves (no in-group predecessor).
 // The header also carries a bound on the size of the ready set: the head moves of all groups
-// plus one per extra successor of a move; the loop keeps ready sets of up to 64*S moves in
-// registers and hands instances above that to the general path.
+// plus one per extra successor of a move.  It is loose (groups become ready one after another),
+// so the loop does not use it: it keeps ready sets of up to 64*S moves in registers and hands
+// an instance to the general path only when its ready set actually grows past that.
 #pragma once
 #include "rr_device.hpp"
 #include "rr.h"

@@ -283,8 +283,10 @@ struct LoopCtx {
     uint32_t alive, out, nb, T;
     int ls, ll;                 // leader position
     uint32_t lc, le, ln, lk;    // leader entry
-    bool err;
+    uint32_t err;               // kNoErr, kOverflow (the general path takes over) or kBroken
 };
+
+enum : uint32_t { kNoErr = 0, kOverflow = 1, kBroken = 2 };
 
 // Compact the ready set into the lowest positions through LDS scratch (index order kept).
 template <int S>
@@ -522,7 +524,7 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
         }
     }
     (void)any_slow;
-    if (!ok) { X.err = true; return; }
+    if (!ok) { X.err = kOverflow; return; }
     // keep the set in slot 0 while it fits there, so that trips stay on the one-slot path
     if (S > 1) {
         uint32_t total = 0;
@@ -537,9 +539,11 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
     if (ldone || moved) find_leader(R, X.ls, X.ll, X.lc, X.le, X.ln, X.lk);
 }
 
-// Alg. 3 iterations of one instance over its loop data M.
+// Alg. 3 iterations of one instance over its loop data M.  Returns true when the ready set
+// outgrew the 64*S register positions: nothing is reported then, the general path redoes the
+// instance from its inputs.
 template <int S, uint32_t flags>
-__device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32_t K, uint32_t G, uint32_t T)
+__device__ __forceinline__ bool loop_run(const Inst &I, const LoopMem &M, uint32_t K, uint32_t G, uint32_t T)
 {
     const int lane = lane_id();
     // ---- initial ready set: head moves of the groups that wait on nothing, in index order
@@ -561,7 +565,7 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
     }
     wave_sync();
     LoopCtx X;
-    X.err = n0 > (uint32_t)(kWave * S);
+    X.err = n0 > (uint32_t)(kWave * S) ? kOverflow : kNoErr;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const uint32_t p = (uint32_t)(s * kWave + lane);
@@ -580,7 +584,7 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
     find_leader(R, X.ls, X.ll, X.lc, X.le, X.ln, X.lk);
 
     while (X.alive > 0) {
-        if (X.nb >= T || X.ls < 0) { X.err = true; break; }   // every batch holds a step: at most T
+        if (X.nb >= T || X.ls < 0) { X.err = kBroken; break; }   // every batch holds a step: at most T
         uint64_t high = 0;
 #pragma unroll
         for (int s = 1; s < S; ++s) high |= R.vm[s];
@@ -589,16 +593,19 @@ __device__ __forceinline__ void loop_run(const Inst &I, const LoopMem &M, uint32
         if (X.err) break;
     }
 
+    if (X.err == kOverflow) return true;
     if (lane == 0) {
         if (X.err) put_info(I.binfo, RR_E_INTERNAL, 0, 0, 0, 0);
         else if (X.nb > I.batch_cap) put_info(I.binfo, RR_E_CAPACITY, 0, 0, X.nb, T);
         else put_info(I.binfo, RR_OK, X.nb, X.out, X.nb, T);
     }
+    return false;
 }
 
-// Run Alg. 3 on one instance whose graph is built (header state ST_FAST, bound <= 64*S).
+// Run Alg. 3 on one instance whose graph is built (header state ST_FAST).  Returns true when
+// the instance goes to the general path.
 template <int S, uint32_t flags>
-__device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t lds_bytes)
+__device__ __forceinline__ bool loop_fast(const Inst &I, uint8_t *lds, uint32_t lds_bytes)
 {
     const int lane = lane_id();
     const Layout L = layout(I.W, I.H, I.move_cap, I.step_cap);
@@ -638,10 +645,10 @@ __device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t 
         for (uint32_t i = lane; i < HN; i += kWave) hd[i] = ghd[i];
         M.mv = mv; M.nx = nx; M.grem = grem; M.gpend = gpend; M.gloff = go; M.hdoff = hdo; M.gl = gl; M.hd = hd;
         wave_sync();
-        loop_run<S, flags>(I, M, K, G, T);   // every LDS access of this copy compiles to ds_* operations
+        return loop_run<S, flags>(I, M, K, G, T);   // every LDS access of this copy compiles to ds_* operations
     } else {
-        // the workspace copy; the mutable counts go to the generic path's region, which is
-        // unused on the fast path
+        // the workspace copy; the mutable counts go to the generic path's region, which the
+        // general path only uses when it redoes the instance
         uint32_t *spare = (uint32_t *)(I.ws + L.gen);
         uint32_t *grem = spare, *gpend = spare + G;
         for (uint32_t i = lane; i < G; i += kWave) {
@@ -651,7 +658,7 @@ __device__ __forceinline__ void loop_fast(const Inst &I, uint8_t *lds, uint32_t 
         M.scratch = (uint4 *)(I.ws + L.scratch);
         M.mv = gmv; M.nx = gnx; M.grem = grem; M.gpend = gpend; M.gloff = ggo; M.hdoff = ghdo; M.gl = ggl; M.hd = ghd;
         wave_sync();
-        loop_run<S, flags>(I, M, K, G, T);
+        return loop_run<S, flags>(I, M, K, G, T);
     }
 }
 

@@ -47,3 +47,19 @@ def test_model_compaction_path():
     b = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=2)
     pb, ps, st = M.loop(g, S, 2)
     assert np.array_equal(pb, b["batch_off"]) and np.array_equal(ps, b["steps"])
+
+
+def test_ready_set_overflow_fixture():
+    """The hand-made wide release outgrows 3 register slots (192 positions) after the first
+    group finishes -- the case where the loop kernel hands the instance to the general path --
+    while its static bound says so too; with 4 slots the model gives the oracle's batches."""
+    from crafted import wide_release
+    shape, mv, goff, n_steps = wide_release()
+    g = M.graph(shape, mv, goff)
+    assert g["bound"] > 192
+    with pytest.raises(RuntimeError, match="overflow"):
+        M.loop(g, 3, 0)
+    for flags in (0, 1, 2):
+        b = oracle.batch(shape, mv, goff, n_steps, flags=flags)
+        pb, ps, _ = M.loop(g, 4, flags)
+        assert np.array_equal(pb, b["batch_off"]) and np.array_equal(ps, b["steps"]), flags

@@ -307,3 +307,64 @@ def test_fast_path_equals_general_path_and_lds_budgets():
                 if r["status"] == 0:
                     rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=flags)
                     same_batch(ref.host_batch(i, binf), rb, f"oracle {i} flags={flags}")
+
+
+def _load_crafted(sb, mv, goff, n_steps):
+    """Put a hand-made move list into a SolveBuffers as if the solve had emitted it."""
+    assert len(mv) <= sb.move_cap and len(goff) - 1 <= sb.group_cap
+    m = np.zeros(sb.move_cap * 4, np.uint16)
+    m[:mv.size] = mv.reshape(-1)
+    sb.moves.copy_(torch.from_numpy(m.view(np.int64)).cuda())
+    g = np.zeros(sb.group_cap + 1, np.uint32)
+    g[:len(goff)] = goff
+    sb.group_off.copy_(torch.from_numpy(g.view(np.int32)).cuda())
+    info = np.zeros(sb.info.numel(), np.uint32)
+    info[:6] = (0, len(mv), len(goff) - 1, n_steps, len(mv), len(goff) - 1)
+    sb.info.copy_(torch.from_numpy(info.view(np.int32)).cuda())
+
+
+def test_ready_set_overflow_hands_over_to_general_path():
+    """A ready set that outgrows the loop's registers mid-run (hand-made wide release: 4 ready
+    moves, then 240 at once on a 64 x 64 grid, whose loop holds 192): the instance is redone on
+    the general path, with the oracle's batches, in one-instance and many-instance launches and
+    with the loop data in LDS and in the workspace."""
+    from crafted import wide_release
+    from paper_2504_06182_amd.pipeline import SolveBuffers, ManyBuffers
+    shape, mv, goff, n_steps = wide_release()
+    say("case overflow single", shape)
+    sb = SolveBuffers(shape)
+    _load_crafted(sb, mv, goff, n_steps)
+    torch.cuda.synchronize()
+    for flags in (0, 1, 2, 1 << 8):
+        rb = oracle.batch(shape, mv, goff, n_steps, flags=flags & 0xFF)
+        same_batch(gpu_batch(sb, n_steps, flags), rb, f"overflow single flags={flags}")
+    say("case overflow many")
+    shots = ri.config_shots("batch64", n=3)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    mb = ManyBuffers(shapes).load([ri.shot_grid(d) for d in shots]).solve()
+    torch.cuda.synchronize()
+    # instance 1 takes the hand-made moves (same 64 x 64 grid; its target is not read here)
+    d1 = mb.desc_np[1]
+    mo, go = int(d1["move_off"]), int(d1["group_off"])
+    assert len(mv) <= int(d1["move_cap"]) and len(goff) - 1 <= int(d1["group_cap"])
+    moves = mb.moves.cpu().numpy().copy()
+    moves[mo:mo + len(mv)] = np.ascontiguousarray(mv).reshape(-1).view(np.int64)
+    mb.moves.copy_(torch.from_numpy(moves).cuda())
+    groups = mb.groups.cpu().numpy().copy()
+    groups[go:go + len(goff)] = goff.view(np.int32)
+    mb.groups.copy_(torch.from_numpy(groups).cuda())
+    sinf = mb.solve_infos().copy()
+    sinf[1, :6] = (0, len(mv), len(goff) - 1, n_steps, len(mv), len(goff) - 1)
+    mb.sinfo.copy_(torch.from_numpy(sinf.reshape(-1).view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    mb.plan_batches([max(int(i[3]), 1) for i in sinf])
+    for flags in (0, 1, 2, 1 << 8):
+        mb.batch(flags=flags)
+        torch.cuda.synchronize()
+        binf = mb.batch_infos()
+        rb = oracle.batch(shape, mv, goff, n_steps, flags=flags & 0xFF)
+        same_batch(mb.host_batch(1, binf), rb, f"overflow many flags={flags}")
+        for i in (0, 2):
+            r = oracle.solve(shapes[i], ri.shot_grid(shots[i]))
+            rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF)
+            same_batch(mb.host_batch(i, binf), rb, f"overflow neighbour {i} flags={flags}")
