@@ -275,7 +275,7 @@ static Plan make_plan(uint32_t flags, uint32_t max_w, uint32_t max_h, bool singl
     P.S = loop_slots(side);
     const uint32_t gkib = (flags >> 24) & 0xFFu;
     if (gkib) P.graph_lds = gkib * 1024u;
-    else P.graph_lds = single ? 120u * 1024u : (side <= 64 ? 64u * 1024u : 0u);
+    else P.graph_lds = single ? 120u * 1024u : 64u * 1024u;
     if (P.graph_lds + sizeof(fast::GraphShared) > lim) P.graph_lds = lim - (uint32_t)sizeof(fast::GraphShared);
     uint32_t kib = (flags >> 8) & 0xFFu;
     if (kib == 0) kib = single ? 64u : 1u;

@@ -140,6 +140,7 @@ struct GraphShared {
     uint32_t part[kGWaves];
     uint32_t red[kGWaves];
     uint32_t flags;
+    uint32_t nr;            // row ranges of the tiled build
 };
 
 __device__ __forceinline__ uint32_t add_wg32(uint32_t *p, uint32_t v)
@@ -233,6 +234,9 @@ __device__ __forceinline__ void set_add(uint32_t (&s)[kMaxPreds], int &n, uint32
         if (i == n) s[i] = v;
     ++n;
 }
+
+__device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+                                          uint32_t T);
 
 // The graph of one instance from its validated moves; cell (W*H + 1 words), grp (K) and touch
 // (K + T) are the per-trap scratch arrays.
@@ -332,6 +336,23 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
         if (tid == 0) hdr[H_STATE] = ST_GENERIC;
         return;
     }
+    graph_tail(I, S, L, K, G, T);
+}
+
+// Second half of the graph build, from the in-group predecessor sets (pend, preds), their
+// successor counts (soff) and the group bit matrix (gbits), all in the workspace: successor
+// lists, release codes, heads, group lists and the header.
+__device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+                                          uint32_t T)
+{
+    const int tid = threadIdx.x;
+    uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
+    uint16_t *nx = (uint16_t *)(I.ws + L.nx);
+    uint32_t *soff = (uint32_t *)(I.ws + L.soff), *sfill = (uint32_t *)(I.ws + L.sfill);
+    uint32_t *slist = (uint32_t *)(I.ws + L.slist), *pend = (uint32_t *)(I.ws + L.pend);
+    uint16_t *preds = (uint16_t *)(I.ws + L.preds);
+    uint32_t *gbits = (uint32_t *)(I.ws + L.gbits), *gcnt = (uint32_t *)(I.ws + L.gcnt), *hcnt = (uint32_t *)(I.ws + L.hcnt);
+    const uint32_t GW = L.GW;
 
     // ---- successor lists (CSR) and release codes
     block_scan(soff, K, S);
@@ -393,6 +414,241 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
     }
 }
 
+// Visit the traps of the path (sx, sy) -> (dx, sy) -> (dx, dy) that lie in rows [y0, y1):
+// f(c) for each trap index c = y * W + x, the horizontal leg first.
+template <class F>
+__device__ __forceinline__ void walk_rows(int W, int sx, int sy, int dx, int dy, int y0, int y1, F &&f)
+{
+    if (sy >= y0 && sy < y1) {
+        const int hx = iabs(dx - sx), st = dx >= sx ? 1 : -1;
+        int c = sy * W + sx;
+        for (int s = 0; s <= hx; ++s, c += st) f(c);
+    }
+    const int vy = iabs(dy - sy);
+    if (vy) {
+        int lo, hi;                             // steps v (1..vy) of the vertical leg inside the rows
+        if (dy > sy) { lo = max(1, y0 - sy); hi = min(vy, y1 - 1 - sy); }
+        else { lo = max(1, sy - y1 + 1); hi = min(vy, sy - y0); }
+        const int st = dy > sy ? W : -W;
+        int c = (dy > sy ? sy + lo : sy - lo) * W + dx;
+        for (int v = lo; v <= hi; ++v, c += st) f(c);
+    }
+}
+
+// Tiled build, for instances whose per-trap arrays exceed the LDS budget: the grid is cut into
+// ranges of whole rows whose trap counts, offsets and touch lists fit in LDS together; each
+// range runs count -> scan -> scatter -> previous touchers for the moves whose path
+// crosses it (per-range move lists, built first), and every move's in-group predecessor set
+// accumulates in the workspace over the ranges it crosses.  Same results as the one-piece
+// build.  Returns false, having changed nothing the workspace build does not redo, when a
+// single row does not fit.
+__device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+                                            uint32_t T, uint8_t *lds, uint32_t lds_bytes)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    const int W = I.W, H = I.H;
+    uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
+    uint32_t *mv32 = (uint32_t *)(I.ws + L.mv);
+    uint32_t *soff = (uint32_t *)(I.ws + L.soff), *sfill = (uint32_t *)(I.ws + L.sfill);
+    uint32_t *pend = (uint32_t *)(I.ws + L.pend);
+    uint16_t *preds = (uint16_t *)(I.ws + L.preds);
+    uint32_t *gbits = (uint32_t *)(I.ws + L.gbits);
+    uint16_t *grp = (uint16_t *)(I.ws + L.grp);
+    uint16_t *rlist = (uint16_t *)(I.ws + L.touch);        // per-range move lists (at most K + T entries)
+    const uint32_t GW = L.GW;
+
+    // LDS: rowc (H + 1 words: row visit counts, then their inclusive prefix), rs (H + 1: first
+    // row of each range), roff (H + 1: move-list offsets), rrow (H halves: range of each row),
+    // then the tile: a range's cell offsets (4 B per trap + 4) and touch lists (2 B per visit)
+    const size_t fixed = al256(12 * ((size_t)H + 1) + 2 * (size_t)H);
+    if (fixed + 1024 > lds_bytes) return false;
+    uint32_t *rowc = (uint32_t *)lds, *rs = rowc + (H + 1), *roff = rs + (H + 1);
+    uint16_t *rrow = (uint16_t *)(roff + (H + 1));
+    uint8_t *tile = lds + fixed;
+    const uint32_t tile_bytes = lds_bytes - (uint32_t)fixed;
+
+    // ---- set-up; visits per row through a difference array
+    for (uint32_t g = tid; g < G; g += kGT)
+        for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b) grp[b] = (uint16_t)g;
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        mv32[b] = (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
+        sfill[b] = 0;
+        pend[b] = 0;
+    }
+    for (uint32_t b = tid; b <= K; b += kGT) soff[b] = 0;
+    for (uint32_t i = tid; i < G * GW; i += kGT) gbits[i] = 0;
+    for (int y = tid; y <= H; y += kGT) rowc[y] = 0;
+    if (tid == 0) S.flags = 0;
+    __syncthreads();
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const uint32_t nh = (uint32_t)iabs(dx - sx) + 1u;
+        add_wg32(&rowc[sy], nh);
+        add_wg32(&rowc[sy + 1], 0u - nh);
+        if (dy != sy) {
+            const int vlo = dy > sy ? sy + 1 : dy, vhi = dy > sy ? dy : sy - 1;
+            add_wg32(&rowc[vlo], 1u);
+            add_wg32(&rowc[vhi + 1], 0xFFFFFFFFu);
+        }
+    }
+    __syncthreads();
+
+    // ---- row ranges (one wave): prefix of the row counts, then greedy ranges of up to 64 rows
+    if (wid == 0) {
+        uint32_t acc = 0, carry = 0;            // acc: difference prefix; carry: visits before the chunk
+        for (int y0 = 0; y0 < H; y0 += kWave) {
+            const int y = y0 + lane;
+            const uint32_t dv = y < H ? rowc[y] : 0u;
+            const uint32_t cnt = acc + (uint32_t)wave_incl_scan((int)dv);      // visits of row y
+            acc = (uint32_t)__shfl((int)cnt, kWave - 1, kWave);
+            const uint32_t cum = carry + (uint32_t)wave_incl_scan((int)cnt);   // visits of rows <= y
+            carry = (uint32_t)__shfl((int)cum, kWave - 1, kWave);
+            if (y < H) rowc[y] = cum;
+        }
+        wave_sync();
+        uint32_t nr = 0, before = 0;
+        bool bad = false;
+        for (int y0 = 0; y0 < H && !bad;) {
+            const int y1 = y0 + 1 + lane;       // candidate end (exclusive)
+            bool fits = false;
+            if (y1 <= H) {
+                const uint64_t need = 4ull * ((uint64_t)(y1 - y0) * W + 1) + 2ull * (rowc[y1 - 1] - before);
+                fits = need <= tile_bytes;
+            }
+            const int n = popc(ballot(fits));   // the cost grows with y1: the fitting ends are a prefix
+            if (n == 0) { bad = true; break; }
+            if (lane == 0) rs[nr] = (uint32_t)y0;
+            for (int y = y0 + lane; y < y0 + n; y += kWave) rrow[y] = (uint16_t)nr;
+            before = rowc[y0 + n - 1];
+            ++nr;
+            y0 += n;
+        }
+        if (lane == 0) {
+            rs[nr] = (uint32_t)H;
+            S.nr = nr;
+            if (bad) S.flags = 2;
+        }
+    }
+    __syncthreads();
+    if (S.flags) return false;
+    const uint32_t R = S.nr;
+
+    // ---- per-range move lists: a path's rows are contiguous, so a move lies in ranges ra..rb
+    for (uint32_t r = tid; r <= R; r += kGT) roff[r] = 0;
+    __syncthreads();
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const uint32_t ra = rrow[min(sy, dy)], rb = rrow[max(sy, dy)];
+        for (uint32_t r = ra; r <= rb; ++r) add_wg32(&roff[r], 1u);
+    }
+    __syncthreads();
+    block_scan(roff, R, S);
+    for (uint32_t b = tid; b < K; b += kGT) {
+        int sx, sy, dx, dy;
+        load_move(I.moves, b, sx, sy, dx, dy);
+        const uint32_t ra = rrow[min(sy, dy)], rb = rrow[max(sy, dy)];
+        for (uint32_t r = ra; r <= rb; ++r) rlist[add_wg32(&roff[r], 1u)] = (uint16_t)b;
+    }
+    __syncthreads();                            // roff[r] is now the end of range r's list
+
+    // ---- the ranges
+    for (uint32_t r = 0; r < R; ++r) {
+        const int y0 = (int)rs[r], y1 = (int)rs[r + 1];
+        const uint32_t c0 = (uint32_t)(y0 * W), nc = (uint32_t)((y1 - y0) * W);
+        uint32_t *cell = (uint32_t *)tile;
+        uint16_t *touch = (uint16_t *)(tile + 4 * ((size_t)nc + 1));
+        const uint32_t mlo = r ? roff[r - 1] : 0u, mhi = roff[r];
+        for (uint32_t c = tid; c <= nc; c += kGT) cell[c] = 0;
+        __syncthreads();
+        for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
+            int sx, sy, dx, dy;
+            load_move(I.moves, rlist[t], sx, sy, dx, dy);
+            walk_rows(W, sx, sy, dx, dy, y0, y1, [&](int c) { add_wg32(&cell[(uint32_t)c - c0], 1u); });
+        }
+        __syncthreads();
+        block_scan(cell, nc, S);
+        for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
+            const uint32_t b = rlist[t];
+            int sx, sy, dx, dy;
+            load_move(I.moves, b, sx, sy, dx, dy);
+            walk_rows(W, sx, sy, dx, dy, y0, y1,
+                      [&](int c) { touch[add_wg32(&cell[(uint32_t)c - c0], 1u)] = (uint16_t)b; });
+        }
+        __syncthreads();
+        // previous toucher of every visit in the range: the largest index below b on the
+        // trap's list, read unsorted two entries at a time (the lists are short; a scan of
+        // independent reads beats sorting them and searching)
+        const uint32_t *t32 = (const uint32_t *)touch;
+        for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
+            const uint32_t b = rlist[t];
+            int sx, sy, dx, dy;
+            load_move(I.moves, b, sx, sy, dx, dy);
+            const uint32_t g = grp[b], glo = I.goff[g];     // b's group holds the moves glo..
+            uint32_t ps[kMaxPreds];
+            int np = 0;
+            bool loaded = false, changed = false, ovf = false;
+            uint32_t last = 0xFFFFFFFFu, lastg = 0xFFFFFFFFu;
+            walk_rows(W, sx, sy, dx, dy, y0, y1, [&](int cg) {
+                const uint32_t c = (uint32_t)cg - c0;
+                const uint32_t lo = c ? cell[c - 1] : 0u, hi = cell[c];
+                uint32_t best = 0;              // previous toucher + 1, 0 when b is the first
+                for (uint32_t w = lo >> 1; w < (hi + 1) >> 1; ++w) {
+                    const uint32_t v = t32[w], x0 = v & 0xFFFFu, x1 = v >> 16;
+                    best = (2 * w >= lo && x0 < b && x0 >= best) ? x0 + 1 : best;
+                    best = (2 * w + 1 < hi && x1 < b && x1 >= best) ? x1 + 1 : best;
+                }
+                if (best == 0) return;
+                const uint32_t a = best - 1;
+                if (a == last) return;
+                last = a;
+                if (a >= glo) {                 // same group (a < b)
+                    if (!loaded) {
+                        np = (int)pend[b];
+#pragma unroll
+                        for (int i = 0; i < kMaxPreds; ++i)
+                            if (i < np) ps[i] = preds[(size_t)b * kMaxPreds + i];
+                        loaded = true;
+                    }
+                    const int before = np;
+                    set_add(ps, np, a, ovf);
+                    changed |= np != before;
+                } else {
+                    const uint32_t ga = grp[a];
+                    if (ga != lastg) {
+                        lastg = ga;
+                        __hip_atomic_fetch_or(&gbits[g * GW + ga / 32], 1u << (ga & 31), __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+            });
+            if (changed) {
+                pend[b] = (uint32_t)np;
+#pragma unroll
+                for (int i = 0; i < kMaxPreds; ++i)
+                    if (i < np) preds[(size_t)b * kMaxPreds + i] = (uint16_t)ps[i];
+            }
+            if (ovf) S.flags = 1;
+        }
+        __syncthreads();
+    }
+    if (S.flags) {
+        if (tid == 0) hdr[H_STATE] = ST_GENERIC;
+        return true;
+    }
+    // ---- successor counts, then the common second half
+    for (uint32_t b = tid; b < K; b += kGT) {
+        const uint32_t np = pend[b];
+        for (uint32_t i = 0; i < np; ++i) add_wg32(&soff[preds[(size_t)b * kMaxPreds + i]], 1u);
+    }
+    __syncthreads();
+    graph_tail(I, S, L, K, G, T);
+    return true;
+}
+
 // Build the graph of one instance (whole workgroup).  lds: dynamic LDS of lds_bytes bytes.
 __device__ void graph_build(const Inst &I, GraphShared &S, uint8_t *lds, uint32_t lds_bytes, bool force_generic)
 {
@@ -448,7 +704,7 @@ __device__ void graph_build(const Inst &I, GraphShared &S, uint8_t *lds, uint32_
         uint16_t *grp = (uint16_t *)(lds + 4 * ((size_t)WH + 1));
         uint16_t *touch = (uint16_t *)(lds + 4 * ((size_t)WH + 1) + 2 * (((size_t)K + 1) & ~(size_t)1));
         graph_core(I, S, L, K, G, T, (uint32_t *)lds, grp, touch);
-    } else {
+    } else if (!graph_tiled(I, S, L, K, G, T, lds, lds_bytes)) {
         graph_core(I, S, L, K, G, T, (uint32_t *)(I.ws + L.cell), (uint16_t *)(I.ws + L.grp),
                    (uint16_t *)(I.ws + L.touch));
     }

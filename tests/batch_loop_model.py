@@ -336,3 +336,89 @@ def graph(shape, moves, goff):
     HN = sum(len(h) for h in heads)
     return dict(K=K, G=G, mv=mv, nx=nx, succ=succ, pend=pend, gw=gw, gpend=gpend, heads=heads,
                 bound=HN + extra, goff=list(goff))
+
+
+def walk_rows(W, m, y0, y1):
+    """Traps of move m = (sx, sy, dx, dy) in rows [y0, y1), as walk_rows (rr_batch_graph.hpp)."""
+    sx, sy, dx, dy = m
+    out = []
+    if y0 <= sy < y1:
+        st = 1 if dx >= sx else -1
+        out += [sy * W + sx + st * s for s in range(abs(dx - sx) + 1)]
+    vy = abs(dy - sy)
+    if vy:
+        if dy > sy: lo, hi = max(1, y0 - sy), min(vy, y1 - 1 - sy)
+        else: lo, hi = max(1, sy - y1 + 1), min(vy, sy - y0)
+        st = 1 if dy > sy else -1
+        out += [(sy + st * v) * W + dx for v in range(lo, hi + 1)]
+    return out
+
+
+def graph_tiled(shape, moves, goff, tile_bytes):
+    """The tiled build (graph_tiled, rr_batch_graph.hpp) step by step: row counts through a
+    difference array, greedy row ranges of at most 64 rows whose cells (4 B + 4) and visits (2 B)
+    fit tile_bytes, per-range move lists, then per range the touch lists and previous touchers.
+    Returns (in-group predecessor sets, group predecessor sets, ranges) or None when a single row
+    does not fit."""
+    W, H = shape[0], shape[1]
+    mvs = [tuple(int(v) for v in m) for m in moves]
+    K = len(mvs); G = len(goff) - 1
+    grp = [0] * K
+    for g in range(G):
+        for b in range(goff[g], goff[g + 1]): grp[b] = g
+    rowc = [0] * (H + 1)
+    for (sx, sy, dx, dy) in mvs:
+        nh = abs(dx - sx) + 1
+        rowc[sy] += nh; rowc[sy + 1] -= nh
+        if dy != sy:
+            vlo, vhi = (sy + 1, dy) if dy > sy else (dy, sy - 1)
+            rowc[vlo] += 1; rowc[vhi + 1] -= 1
+    cum, run, acc = [0] * H, 0, 0
+    for y in range(H):
+        acc += rowc[y]; run += acc; cum[y] = run
+    rs, rrow, y0, before = [], [0] * H, 0, 0
+    while y0 < H:
+        n = 0
+        for lane in range(64):
+            y1 = y0 + 1 + lane
+            if y1 <= H and 4 * ((y1 - y0) * W + 1) + 2 * (cum[y1 - 1] - before) <= tile_bytes: n += 1
+        if n == 0: return None
+        for y in range(y0, y0 + n): rrow[y] = len(rs)
+        rs.append(y0); before = cum[y0 + n - 1]; y0 += n
+    rs.append(H); R = len(rs) - 1
+    lists = [[] for _ in range(R)]
+    for b, (sx, sy, dx, dy) in enumerate(mvs):
+        for r in range(rrow[min(sy, dy)], rrow[max(sy, dy)] + 1): lists[r].append(b)
+    assert sum(len(l) for l in lists) <= K + sum(abs(m[2] - m[0]) + abs(m[3] - m[1]) for m in mvs)
+    preds = [[] for _ in range(K)]; gbits = {}; ovf = False
+    for r in range(R):
+        y0, y1 = rs[r], rs[r + 1]; c0, nc = y0 * W, (y1 - y0) * W
+        touch = {}
+        for b in reversed(lists[r]):            # arbitrary arrival order
+            w = walk_rows(W, mvs[b], y0, y1)
+            assert w, "a listed move has no trap in the range"
+            for c in w:
+                assert c0 <= c < c0 + nc
+                touch.setdefault(c, []).append(b)
+        visits = sum(len(v) for v in touch.values())
+        assert visits == cum[y1 - 1] - (cum[y0 - 1] if y0 else 0)
+        assert 4 * (nc + 1) + 2 * visits <= tile_bytes
+        for c in touch: touch[c].sort()
+        for b in lists[r]:
+            g, glo = grp[b], goff[grp[b]]
+            last = lastg = None
+            for c in walk_rows(W, mvs[b], y0, y1):
+                L = touch[c]
+                if L[0] == b: continue
+                a = max(v for v in L if v < b)
+                if a == last: continue
+                last = a
+                if a >= glo:
+                    if a not in preds[b]:
+                        if len(preds[b]) == 8: ovf = True
+                        else: preds[b].append(a)
+                elif grp[a] != lastg:
+                    lastg = grp[a]
+                    gbits.setdefault(g, set()).add(grp[a])
+    assert not ovf
+    return [set(p) for p in preds], gbits, R

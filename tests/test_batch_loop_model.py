@@ -63,3 +63,36 @@ def test_ready_set_overflow_fixture():
         b = oracle.batch(shape, mv, goff, n_steps, flags=flags)
         pb, ps, _ = M.loop(g, 4, flags)
         assert np.array_equal(pb, b["batch_off"]) and np.array_equal(ps, b["steps"]), flags
+
+
+@pytest.mark.parametrize("tile_kib", [60, 12, 3])
+def test_tiled_graph_equals_one_piece(tile_kib):
+    """The tiled graph build (row ranges in LDS, per-move predecessor sets accumulated over the
+    ranges) gives the one-piece build's predecessor sets and group bit matrix, with few or many
+    ranges; a budget below one row falls back."""
+    shots = [d for d in ri.config_shots("mixed", n=12) if d["w"] <= 96][:4] + ri.config_shots("batch64", n=1)
+    most = 0
+    for d in shots:
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        r = oracle.solve(shape, ri.shot_grid(d))
+        if r["status"] != 0 or len(r["moves"]) == 0:
+            continue
+        g = M.graph(shape, r["moves"], r["group_off"])
+        t = M.graph_tiled(shape, r["moves"], r["group_off"], tile_kib * 1024)
+        if t is None:
+            assert tile_kib == 3
+            continue
+        preds, gbits, R = t
+        want = [set() for _ in range(g["K"])]
+        for a, ss in enumerate(g["succ"]):
+            for b in ss:
+                want[b].add(a)
+        assert preds == want
+        wantg = {}
+        for h, ws in enumerate(g["gw"]):
+            for x in ws:
+                wantg.setdefault(x, set()).add(h)
+        assert {k: v for k, v in gbits.items() if v} == wantg
+        most = max(most, R)
+    if tile_kib < 60:
+        assert most > 1
