@@ -68,10 +68,10 @@ BATCH_SOURCES = ("rr_batch.hip", "rr_batch_graph.hpp", "rr_batch_loop.hpp", "rr_
 PROFILE = os.path.join(ROOT, "profiles", "k_loop_many_batch64.md")
 
 
-def measured_traffic():
+def measured_traffic(flags):
     """HBM bytes of one k_loop_many launch from the committed rocprofv3 PMC summary (FETCH_SIZE +
     WRITE_SIZE scaled by a plain copy), or None when that summary was taken on other kernel
-    sources than the ones built now."""
+    sources, or under another launch schedule (flags), than the ones run now."""
     import hashlib
     import re
     h = hashlib.sha256()
@@ -83,8 +83,8 @@ def measured_traffic():
         text = open(PROFILE).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch k_loop_many<3,0> (\d+) sources_sha256 ([0-9a-f]+)", text)
-    if not m or m.group(2) != sha:
+    m = re.search(r"traffic_bytes_per_launch k_loop_many<3,0> (\d+) sources_sha256 ([0-9a-f]+) flags (\d+)", text)
+    if not m or m.group(2) != sha or int(m.group(3)) != int(flags):
         return None
     return float(m.group(1))
 
@@ -229,6 +229,7 @@ def main():
         rrbuild.build()
     import paper_2504_06182_amd as rr
     from paper_2504_06182_amd.pipeline import BatchBuffers, ManyBuffers, SolveBuffers
+    from paper_2504_06182_amd.tune import flags_for
     rr.lib()
     torch.cuda.set_device(0)
     dev = "cuda:0"
@@ -242,6 +243,8 @@ def main():
     mb.alloc_pools(n * STEP_BOUND_PER_SHOT, n * (STEP_BOUND_PER_SHOT + 1), n * ((ws_one + 255) // 256 * 256))
     stream = torch.cuda.current_stream()
 
+    bflags = flags_for(64, args.flags)          # the tuned launch schedule of the 64 class
+
     def step(ev=None):
         if ev: ev[0].record(stream)
         mb.solve(stream)
@@ -249,10 +252,10 @@ def main():
         mb.plan_device(stream)
         if ev: ev[2].record(stream)
         if ev:
-            mb.batch(args.flags, stream, graph_done_event=ev[3], loop_done_event=ev[4])
+            mb.batch(bflags, stream, graph_done_event=ev[3], loop_done_event=ev[4])
             ev[5].record(stream)
         else:
-            mb.batch(args.flags, stream)
+            mb.batch(bflags, stream)
 
     if args.calib_copy_mib > 0:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.int32, device=dev)
@@ -342,7 +345,7 @@ def main():
 
     value = n / (ms_per_step / 1e3)
     achieved = bytes_batch / (k_loop / 1e3) / 1e9
-    traffic = measured_traffic() if args.traffic_gb is None else args.traffic_gb * 1e9
+    traffic = measured_traffic(bflags) if args.traffic_gb is None else args.traffic_gb * 1e9
     line = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -358,7 +361,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "8192 shots, 64x64 trap grid, i.i.d. Bernoulli(0.55) loading, centred 44x44 "
                                "target; solve + batching (line-or-column constraint) per shot",
-                   "shots": n, "grid": [64, 64], "target": [44, 44], "p": 0.55, "flags": args.flags},
+                   "shots": n, "grid": [64, 64], "target": [44, 44], "p": 0.55, "flags": bflags,
+                   "schedule": {"graph_lds_kib": (bflags >> 24) & 0xFF, "loop_lds_kib": (bflags >> 8) & 0xFF}},
         "kernels_ms": {"solve_many": round(k_solve, 3), "plan_many": round(k_plan, 3), "batch_many": round(k_batch, 3),
                        "batch_graph": round(k_graph, 3), "batch_loop": round(k_loop, 3),
                        "batch_generic": round(k_generic, 3)},

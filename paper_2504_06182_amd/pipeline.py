@@ -10,6 +10,7 @@ import torch
 
 from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_moves_many_staged, rr_batch_workspace_bytes,
                rr_plan_many, rr_solve, rr_solve_many)
+from .tune import flags_for
 
 SOLVE_INFO_WORDS = 6   # rr_solve_info: int32 status + 5 x uint32
 BATCH_INFO_WORDS = 5   # rr_batch_info: int32 status + 4 x uint32
@@ -324,21 +325,22 @@ class ClassedBuffers:
 
     def run(self, flags=0, streams=None):
         """Enqueue every class.  With ``streams`` the classes fork from the current stream onto
-        their own streams and join back (event edges, valid under graph capture)."""
+        their own streams and join back (event edges, valid under graph capture).  Each class
+        batches under its tuned launch schedule unless ``flags`` sets one (tune.flags_for)."""
         if streams is None:
-            for _, _, mb in self.parts:
+            for c, _, mb in self.parts:
                 mb.solve()
                 mb.plan_device()
-                mb.batch(flags)
+                mb.batch(flags_for(c, flags))
             return self
         cur = torch.cuda.current_stream()
-        for k, (_, _, mb) in enumerate(self.parts):
+        for k, (c, _, mb) in enumerate(self.parts):
             st = streams[k % len(streams)]
             st.wait_stream(cur)
             with torch.cuda.stream(st):
                 mb.solve(st)
                 mb.plan_device(st)
-                mb.batch(flags, st)
+                mb.batch(flags_for(c, flags), st)
         for k in range(min(len(streams), len(self.parts))):
             cur.wait_stream(streams[k])
         return self

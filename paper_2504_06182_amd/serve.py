@@ -26,6 +26,7 @@ import numpy as np
 import torch
 
 from . import RR_E_CAPACITY, RR_OK, rr_batch_moves_many, rr_batch_workspace_bytes, rr_solve_many
+from .tune import flags_for
 from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuffers, SolveBuffers, size_class,
                        solve_caps, words_per_row)
 
@@ -160,7 +161,8 @@ class Server:
             w.sinfo = torch.empty(n * SOLVE_INFO_WORDS, dtype=torch.int32, device=self.device)
             w.binfo = torch.empty(n * BATCH_INFO_WORDS, dtype=torch.int32, device=self.device)
             rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo, st)
-            rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, self.flags, c.batches, c.steps,
+            rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, flags_for(c.side, self.flags),
+                                c.batches, c.steps,
                                 w.binfo, c.ws, c.ws.numel() * 8, st)
             w.event = torch.cuda.Event()
             w.event.record(st)
