@@ -280,6 +280,9 @@ static Plan make_plan(uint32_t flags, uint32_t max_w, uint32_t max_h, bool singl
     uint32_t kib = (flags >> 8) & 0xFFu;
     if (kib == 0) kib = single ? 64u : 1u;
     P.loop_lds = kib * 1024u;
+    // the loop always keeps its group counts and merge scratch in LDS
+    const uint32_t small = 8u * fast::fast_group_cap((int)max_w, (int)max_h, 0xFFFFFFFFu) + 16u * kWave * P.S + 16u;
+    if (P.loop_lds < small) P.loop_lds = small;
     if (P.loop_lds > lim) P.loop_lds = lim;
     const uint32_t gkb = kib < 24u ? 24u : kib;
     P.gen_lds = gkb > 56u ? 56u * 1024u : gkb * 1024u;

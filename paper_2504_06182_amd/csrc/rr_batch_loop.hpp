@@ -198,10 +198,11 @@ __device__ __forceinline__ bool insert_ready(Ready<S> &R, const LoopMem &M, uint
 }
 
 // Successors of finished move b (group g) -- unless the caller placed it already -- and, when b
-// was its group's last move, the groups waiting on that group.
+// was its group's last move (group_done: the caller counted the group down), the groups waiting
+// on that group.
 template <int NS, int S>
 __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint32_t b, uint32_t g, int ps, int pl, bool &moved,
-                                             bool successors)
+                                             bool successors, bool group_done)
 {
     const int lane = lane_id();
     bool ok = true;
@@ -219,10 +220,7 @@ __device__ __forceinline__ bool release_move(Ready<S> &R, const LoopMem &M, uint
             if (old == 1u) ok &= insert_ready<NS, S>(R, M, nx, g, ps, pl, moved);
         }
     }
-    uint32_t left = 0;
-    if (lane == 0) left = M.grem[g]--;
-    left = rfl(left);
-    if (left == 1u) {
+    if (group_done) {
         const uint32_t lo = rfl(M.gloff[g]), hi = rfl(M.gloff[g + 1]);
         for (uint32_t t0 = lo; t0 < hi; t0 += kWave) {
             const uint32_t t = t0 + lane;
@@ -420,21 +418,48 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
         }
         const uint32_t ts = wave_min_dpp(tv);
         if (ts > 0) {
-            uint32_t rank = 0;
+            if (ts >= base) {
+                // long convoy: member by member, the lanes write its next ts codes
+                uint32_t rank = 0;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                uint64_t m = acc[s];
-                while (m) {
-                    const int l = ffs64(m);
-                    m &= m - 1;
-                    const uint32_t cm = rdl(R.c[s], l);
-                    const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(cm >> 30) : delta;
-                    for (uint32_t j = lane; j < ts; j += kWave) {
-                        const uint32_t at = X.out + j * base + rank;
-                        if (at < I.step_cap) I.steps[at] = cm + j * dl;
+                for (int s = 0; s < NS; ++s) {
+                    uint64_t m = acc[s];
+                    while (m) {
+                        const int l = ffs64(m);
+                        m &= m - 1;
+                        const uint32_t cm = rdl(R.c[s], l);
+                        const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(cm >> 30) : delta;
+                        for (uint32_t j = lane; j < ts; j += kWave) {
+                            const uint32_t at = X.out + j * base + rank;
+                            if (at < I.step_cap) I.steps[at] = cm + j * dl;
+                        }
+                        ++rank;
                     }
-                    ++rank;
                 }
+            } else {
+                // wide convoy: the members' codes go to LDS in rank order; lane r then writes
+                // member r's next ts codes (one coalesced store per repeat)
+                uint32_t *sc = (uint32_t *)M.scratch;
+                uint32_t rb = 0;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    const uint64_t a = acc[s];
+                    if (!a) continue;
+                    if ((a >> lane) & 1ull) sc[rb + mbcnt(a)] = R.c[s];
+                    rb += (uint32_t)popc(a);
+                }
+                wave_sync();
+                for (uint32_t r0 = 0; r0 < base; r0 += kWave) {
+                    const uint32_t r = r0 + (uint32_t)lane;
+                    if (r < base) {
+                        uint32_t v = sc[r];
+                        const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(v >> 30) : delta;
+                        uint32_t at = X.out + r;
+                        for (uint32_t j = 0; j < ts; ++j, at += base, v += dl)
+                            if (at < I.step_cap) I.steps[at] = v;
+                    }
+                }
+                wave_sync();
             }
             for (uint32_t j = lane; j < ts; j += kWave)
                 if (X.nb + 1 + j <= I.batch_cap) I.boff[X.nb + 1 + j] = X.out + (j + 1) * base;
@@ -489,21 +514,24 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
         slow[s] = 0;
         if (!done[s]) continue;
         dk[s] = R.k[s];
-        uint64_t m = done[s];
-        while (m) {
-            const int l = ffs64(m);
-            m &= m - 1;
-            const uint32_t kk = rdl(dk[s], l);
-            const uint32_t b = kk >> 10;
-            if (rfl(M.nx[b]) == ((kRelNext << 14) | 1u)) {
-                uint32_t c0, e0, n0;
-                entry_of(rfl(M.mv[b + 1]), c0, e0, n0);
-                const uint32_t k0 = kk + (1u << 10);
-                if (lane == l) { R.c[s] = c0; R.e[s] = e0; R.n[s] = n0; R.k[s] = k0; }
-                if (s == X.ls && l == X.ll) { X.lc = c0; X.le = e0; X.ln = n0; X.lk = k0; ldone = false; }
-            } else {
-                slow[s] |= 1ull << l;
-            }
+        // every finished lane of the slot reads its release code and the next move at once
+        const bool me = (done[s] >> lane) & 1ull;
+        uint32_t code = 0, nm = 0;
+        if (me) {
+            const uint32_t b = R.k[s] >> 10;
+            code = M.nx[b];
+            nm = M.mv[b + 1];                   // the array holds move_cap + 1 words
+        }
+        const bool fast = me && code == ((kRelNext << 14) | 1u);
+        if (fast) {
+            uint32_t c0, e0, n0;
+            entry_of(nm, c0, e0, n0);
+            R.c[s] = c0; R.e[s] = e0; R.n[s] = n0; R.k[s] += 1u << 10;
+        }
+        slow[s] = ballot(me && !fast);
+        if (s == X.ls && ((done[s] & ~slow[s]) >> X.ll) & 1ull) {
+            X.lc = rdl(R.c[s], X.ll); X.le = rdl(R.e[s], X.ll); X.ln = rdl(R.n[s], X.ll); X.lk = rdl(R.k[s], X.ll);
+            ldone = false;
         }
         if (slow[s]) {
             if ((slow[s] >> lane) & 1ull) { R.c[s] = kInv; R.k[s] = kInv; }
@@ -512,15 +540,28 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
         }
     }
     X.alive -= ndone;
+    // every finished lane counts its group down at once; the last one of a group frees the
+    // groups waiting on it
+    uint64_t gdone[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        gdone[s] = 0;
+        if (!done[s]) continue;
+        const bool me = (done[s] >> lane) & 1ull;
+        uint32_t old = 0;
+        if (me) old = __hip_atomic_fetch_sub(&M.grem[dk[s] & 0x3FFu], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        gdone[s] = ballot(me && old == 1u);
+    }
     bool moved = false, ok = true;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        uint64_t m = done[s];
+        uint64_t m = slow[s] | gdone[s];
         while (m) {
             const int l = ffs64(m);
             m &= m - 1;
             const uint32_t kk = rdl(dk[s], l);
-            ok &= release_move<NS, S>(R, M, kk >> 10, kk & 0x3FFu, s, l, moved, ((slow[s] >> l) & 1ull) != 0);
+            ok &= release_move<NS, S>(R, M, kk >> 10, kk & 0x3FFu, s, l, moved, ((slow[s] >> l) & 1ull) != 0,
+                                      ((gdone[s] >> l) & 1ull) != 0);
         }
     }
     (void)any_slow;
@@ -647,15 +688,17 @@ __device__ __forceinline__ bool loop_fast(const Inst &I, uint8_t *lds, uint32_t 
         wave_sync();
         return loop_run<S, flags>(I, M, K, G, T);   // every LDS access of this copy compiles to ds_* operations
     } else {
-        // the workspace copy; the mutable counts go to the generic path's region, which the
-        // general path only uses when it redoes the instance
-        uint32_t *spare = (uint32_t *)(I.ws + L.gen);
-        uint32_t *grem = spare, *gpend = spare + G;
+        // the workspace copy: the move data stays in the workspace, but the per-group counts
+        // (read and written at every finished move) and the merge scratch live in LDS -- the
+        // launch plan gives every launch room for them (loop_small_lds)
+        const size_t sat = (8 * (size_t)G + 15) & ~(size_t)15;
+        if (sat + 16 * (size_t)kWave * S > lds_bytes) return true;    // not reached: the general path
+        uint32_t *grem = (uint32_t *)lds, *gpend = grem + G;
         for (uint32_t i = lane; i < G; i += kWave) {
             grem[i] = I.goff[i + 1] - I.goff[i];
             gpend[i] = ggp[i];
         }
-        M.scratch = (uint4 *)(I.ws + L.scratch);
+        M.scratch = (uint4 *)(lds + sat);
         M.mv = gmv; M.nx = gnx; M.grem = grem; M.gpend = gpend; M.gloff = ggo; M.hdoff = ghdo; M.gl = ggl; M.hd = ghd;
         wave_sync();
         return loop_run<S, flags>(I, M, K, G, T);
