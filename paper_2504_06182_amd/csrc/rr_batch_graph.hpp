@@ -14,7 +14,9 @@
 // Construction, all by counting: per-trap toucher counts (atomics) -> exclusive scan ->
 // scatter of move indices -> each trap's list sorted by index -> each move walks its path and
 // looks itself up in every list it is on to find its previous toucher.  The per-trap arrays
-// live in LDS when they fit the launch's budget, else in the workspace.
+// live in LDS when they fit the launch's budget; larger grids are built in LDS tiles of whole
+// rows (graph_tiled, which scans the unsorted lists instead: there they are long and uneven);
+// a row too large for the budget falls back to the workspace.
 //
 // Output (workspace, read by the loop kernel): for every move its packed coordinates and a
 // 16-bit release code (no successor / exactly one successor that waits on nothing else / a

@@ -418,49 +418,33 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
         }
         const uint32_t ts = wave_min_dpp(tv);
         if (ts > 0) {
-            if (ts >= base) {
-                // long convoy: member by member, the lanes write its next ts codes
-                uint32_t rank = 0;
+            // the members' codes go to LDS in rank order; then the ts x base new steps are
+            // written lane-parallel in output order: entry i is repeat i / base of member i % base
+            uint32_t *sc = (uint32_t *)M.scratch;
+            uint32_t rb = 0;
 #pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    uint64_t m = acc[s];
-                    while (m) {
-                        const int l = ffs64(m);
-                        m &= m - 1;
-                        const uint32_t cm = rdl(R.c[s], l);
-                        const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(cm >> 30) : delta;
-                        for (uint32_t j = lane; j < ts; j += kWave) {
-                            const uint32_t at = X.out + j * base + rank;
-                            if (at < I.step_cap) I.steps[at] = cm + j * dl;
-                        }
-                        ++rank;
-                    }
-                }
-            } else {
-                // wide convoy: the members' codes go to LDS in rank order; lane r then writes
-                // member r's next ts codes (one coalesced store per repeat)
-                uint32_t *sc = (uint32_t *)M.scratch;
-                uint32_t rb = 0;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    const uint64_t a = acc[s];
-                    if (!a) continue;
-                    if ((a >> lane) & 1ull) sc[rb + mbcnt(a)] = R.c[s];
-                    rb += (uint32_t)popc(a);
-                }
-                wave_sync();
-                for (uint32_t r0 = 0; r0 < base; r0 += kWave) {
-                    const uint32_t r = r0 + (uint32_t)lane;
-                    if (r < base) {
-                        uint32_t v = sc[r];
-                        const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(v >> 30) : delta;
-                        uint32_t at = X.out + r;
-                        for (uint32_t j = 0; j < ts; ++j, at += base, v += dl)
-                            if (at < I.step_cap) I.steps[at] = v;
-                    }
-                }
-                wave_sync();
+            for (int s = 0; s < NS; ++s) {
+                const uint64_t a = acc[s];
+                if (!a) continue;
+                if ((a >> lane) & 1ull) sc[rb + mbcnt(a)] = R.c[s];
+                rb += (uint32_t)popc(a);
             }
+            wave_sync();
+            const uint32_t total = ts * base;
+            const float inv = 1.0f / (float)base;
+            for (uint32_t i0 = 0; i0 < total; i0 += kWave) {
+                const uint32_t i = i0 + (uint32_t)lane;
+                if (i < total) {
+                    uint32_t j = (uint32_t)((float)i * inv);          // i / base, give or take one
+                    while (j * base > i) --j;
+                    while ((j + 1) * base <= i) ++j;
+                    const uint32_t v = sc[i - j * base];
+                    const uint32_t dl = flags == RR_LAMBDA_NONE ? step_delta(v >> 30) : delta;
+                    const uint32_t at = X.out + i;
+                    if (at < I.step_cap) I.steps[at] = v + j * dl;
+                }
+            }
+            wave_sync();
             for (uint32_t j = lane; j < ts; j += kWave)
                 if (X.nb + 1 + j <= I.batch_cap) I.boff[X.nb + 1 + j] = X.out + (j + 1) * base;
             X.out += ts * base;

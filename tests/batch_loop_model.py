@@ -256,7 +256,9 @@ def loop(Gd, S, flags):
 
 
 def graph(shape, moves, goff):
-    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other."""
+    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other.  The
+    kernel scans each trap's unsorted list for the largest index below the walking move; the model
+    sorts the lists and searches them, which finds the same previous toucher."""
     W, H = shape[0], shape[1]
     K = len(moves); G = len(goff) - 1; WH = W * H
     mvs = [tuple(int(v) for v in m) for m in moves]
