@@ -256,9 +256,7 @@ def loop(Gd, S, flags):
 
 
 def graph(shape, moves, goff):
-    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other.  The
-    kernel scans each trap's unsorted list for the largest index below the walking move; the model
-    sorts the lists and searches them, which finds the same previous toucher."""
+    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other."""
     W, H = shape[0], shape[1]
     K = len(moves); G = len(goff) - 1; WH = W * H
     mvs = [tuple(int(v) for v in m) for m in moves]
@@ -359,7 +357,9 @@ def walk_rows(W, m, y0, y1):
 def graph_tiled(shape, moves, goff, tile_bytes):
     """The tiled build (graph_tiled, rr_batch_graph.hpp) step by step: row counts through a
     difference array, greedy row ranges of at most 64 rows whose cells (4 B + 4) and visits (2 B)
-    fit tile_bytes, per-range move lists, then per range the touch lists and previous touchers.
+    fit tile_bytes, per-range move lists, then per range the touch lists and previous touchers
+    (the kernel scans each unsorted list for the largest index below the walking move; the model
+    sorts and takes the maximum below, the same previous toucher).
     Returns (in-group predecessor sets, group predecessor sets, ranges) or None when a single row
     does not fit."""
     W, H = shape[0], shape[1]
