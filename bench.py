@@ -151,6 +151,88 @@ def mixed_graph_form(args, dev, replays):
 
 
 
+def paper_geometry_form(args, dev, n_single):
+    """The paper's benchmark geometry (32 x 54 traps, full-width 32 x 32 target, exactly 1036 atoms
+    per shot, 1000 shots): per-shot latency of one synchronised rr_solve launch -- the paper
+    reports red-rec time per instance -- and of solve + batching, and the per-shot cost when all
+    1000 shots go in one launch of each."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import rr_inputs as ri
+    from paper_2504_06182_amd.pipeline import BatchBuffers, ManyBuffers, SolveBuffers
+    from paper_2504_06182_amd.tune import flags_for
+
+    shots = ri.config_shots("paper32")
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    stream = torch.cuda.current_stream()
+    sbs = [SolveBuffers(shapes[i], device=dev).load(grids[i]) for i in range(n_single)]
+    for sb in sbs:
+        sb.run(stream)
+    torch.cuda.synchronize()
+    steps = [max(sb.host()["n_steps"], 1) for sb in sbs]
+    bbs = [BatchBuffers(sb, step_cap=st, device=dev) for sb, st in zip(sbs, steps)]
+    for sb, bb in zip(sbs[:4], bbs[:4]):
+        sb.run(stream); bb.run(args.flags, stream)
+    torch.cuda.synchronize()
+    lat_s, lat_b = [], []
+    for sb in sbs:
+        a = time.perf_counter()
+        sb.run(stream)
+        torch.cuda.synchronize()
+        lat_s.append((time.perf_counter() - a) * 1e6)
+    for sb, bb in zip(sbs, bbs):
+        a = time.perf_counter()
+        sb.run(stream)
+        bb.run(args.flags, stream)
+        torch.cuda.synchronize()
+        lat_b.append((time.perf_counter() - a) * 1e6)
+    exact = 0
+    for sb, bb, i in zip(sbs[:8], bbs[:8], range(8)):
+        g, r = sb.host(), oracle.solve(shapes[i], grids[i])
+        gb = bb.host()
+        rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=args.flags & 0xFF)
+        exact += int(g["status"] == r["status"] == 0 and np.array_equal(g["moves"], r["moves"])
+                     and np.array_equal(g["final"], r["final"]) and np.array_equal(gb["steps"], rb["steps"])
+                     and np.array_equal(gb["batch_off"], rb["batch_off"]))
+
+    mb = ManyBuffers(shapes, device=dev).load(grids).solve(stream)
+    torch.cuda.synchronize()
+    mb.plan_batches([max(int(i[3]), 1) for i in mb.solve_infos()])
+    bflags = flags_for(64, args.flags)
+    ts, tb = [], []
+    for _ in range(6):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        mb.solve(stream)
+        e[1].record(stream)
+        mb.batch(bflags, stream)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        ts.append(e[0].elapsed_time(e[1]))
+        tb.append(e[1].elapsed_time(e[2]))
+    n = len(shots)
+    infeasible = int((mb.solve_infos()[:, 0].view(np.int32) == 1).sum())
+    ts, tb = float(np.median(ts[1:])), float(np.median(tb[1:]))
+    return {"workload": "the paper's geometry: 32 x 54 traps, full-width centred 32 x 32 target, exactly 1036 atoms "
+                        "per shot drawn uniformly, 1000 shots",
+            "shots": n, "infeasible": infeasible,
+            "per_launch_solve_p50_us": round(float(np.percentile(lat_s, 50)), 1),
+            "per_launch_solve_p99_us": round(float(np.percentile(lat_s, 99)), 1),
+            "per_launch_solve_batch_p50_us": round(float(np.percentile(lat_b, 50)), 1),
+            "per_launch_solve_batch_p99_us": round(float(np.percentile(lat_b, 99)), 1),
+            "per_launch_sample": n_single,
+            "batched_solve_us_per_shot": round(ts * 1e3 / n, 3),
+            "batched_solve_batch_us_per_shot": round((ts + tb) * 1e3 / n, 3),
+            "batched_launch_ms": {"solve": round(ts, 3), "batch": round(tb, 3)},
+            "bit_exact_sample": f"{exact}/8",
+            "paper_context": {"red_rec_serial_cpu_us": 106, "red_rec_gpu_us": 197,
+                              "hardware": "AMD Threadripper 2950X (CPU) / Nvidia Quadro RTX 4000 (GPU)",
+                              "note": "mean time per instance over 1000 instances; batching not timed there"}}
+
+
 def served_form(args, dev):
     """Served stream: Poisson arrivals at --serve-rate shots/s for --serve-seconds of the uneven
     mix (grid side uniform over {32..256}), fed to the continuous-batching server; per-shot
@@ -201,6 +283,8 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="batching constraint (0 line-or-column, 1 along, 2 none)")
     ap.add_argument("--traffic-gb", type=float, default=None, help="HBM bytes of one batching launch from PMC")
     ap.add_argument("--mixed-replays", type=int, default=3, help="graph replays of the uneven batch (0: skip)")
+    ap.add_argument("--paper-shots", type=int, default=200,
+                    help="shots of the paper's geometry timed one launch at a time (0: skip the form)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="served stream length (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-pool", type=int, default=1024)
@@ -340,6 +424,7 @@ def main():
     per_launch_sps = len(per) / (tp1 - tp0)
     lat = np.array(lat)
 
+    paper = paper_geometry_form(args, dev, args.paper_shots) if args.paper_shots > 0 else None
     mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
     served = served_form(args, dev) if args.serve_seconds > 0 else None
 
@@ -379,7 +464,7 @@ def main():
                   "per_launch_p99_us": round(float(np.percentile(lat, 99)), 1),
                   "per_launch_sample": len(lat),
                   "batched_step_latency_us": round(ms_per_step * 1e3, 1),
-                  "mixed_graph": mixed,
+                  "paper_geometry": paper, "mixed_graph": mixed,
                   "served": served},
         "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
                            "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),

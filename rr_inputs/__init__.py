@@ -10,6 +10,8 @@ generators", OOPSLA 2014), used as a counter-based hash of a 64-bit key.
 * cell key      = seed << 48  ^  shot << 24  ^  y << 12  ^  x          (x, y < 4096)
 * shot-level key = (seed | 0x8000) << 48  ^  shot << 24  ^  j          (j = draw index)
 * a cell is loaded iff (splitmix64(key) >> 32) < floor(p * 2**32)      (i.i.d. Bernoulli(p))
+* fixed-count loading (exactly n atoms, uniform over the n-subsets of traps): the n cells with
+  the smallest splitmix64(cell key), ties broken by cell index y*W + x
 
 Layout of a packed grid: ``uint64[H][ws]`` with ``ws = ceil(W/64)``; bit ``x % 64`` of word
 ``y*ws + x//64`` is trap (x, y); columns run left to right, rows bottom to top; padding bits
@@ -20,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "splitmix64", "bernoulli_grid", "pack_rows", "unpack_rows", "words_per_row",
+    "splitmix64", "bernoulli_grid", "fixed_count_grid", "pack_rows", "unpack_rows", "words_per_row",
     "centred_target", "config_shots", "CONFIGS", "uniform01",
 ]
 
@@ -46,6 +48,19 @@ def bernoulli_grid(seed: int, shot: int, w: int, h: int, p: float) -> np.ndarray
     key = (np.uint64(seed) << np.uint64(48)) ^ (np.uint64(shot) << np.uint64(24)) ^ (ys << np.uint64(12)) ^ xs
     thr = np.uint64(int(p * 4294967296.0))
     return ((splitmix64(key) >> np.uint64(32)) < thr).astype(np.uint8)
+
+
+def fixed_count_grid(seed: int, shot: int, w: int, h: int, n: int) -> np.ndarray:
+    """Dense ``uint8[h][w]`` occupancy with exactly n loaded cells, drawn uniformly: the n cells
+    of smallest hash (cell keys as for bernoulli_grid), ties broken by cell index."""
+    if not 0 <= n <= w * h:
+        raise ValueError("atom count outside 0..W*H")
+    ys, xs = np.meshgrid(np.arange(h, dtype=np.uint64), np.arange(w, dtype=np.uint64), indexing="ij")
+    key = (np.uint64(seed) << np.uint64(48)) ^ (np.uint64(shot) << np.uint64(24)) ^ (ys << np.uint64(12)) ^ xs
+    order = np.argsort(splitmix64(key).reshape(-1), kind="stable")
+    dense = np.zeros(w * h, dtype=np.uint8)
+    dense[order[:n]] = 1
+    return dense.reshape(h, w)
 
 
 def uniform01(seed: int, shot: int, j: int) -> float:
@@ -90,6 +105,9 @@ CONFIGS = {
     "batch64": dict(n=8192, side=64, s=44, p=0.55, seed=3),
     "mixed": dict(n=4096, sides=MIX_SIDES, frac=0.7, p_lo=0.5, p_hi=0.65, seed=4),
     "big1024": dict(n=1, side=1024, s=780, p=0.6, seed=5),
+    # the paper's benchmark geometry: N_tx = 32 columns, N_ty = ceil(N_tx / 0.6) = 54 rows, a
+    # full-width 32 x 32 target (centre-compact), exactly floor(0.6 * 32 * 54) = 1036 atoms
+    "paper32": dict(n=1000, w=32, h=54, sw=32, sh=32, count=1036, seed=6),
 }
 
 
@@ -99,6 +117,11 @@ def config_shots(name: str, n: int | None = None, first: int = 0):
     total = c["n"] if n is None else n
     shots = []
     for i in range(first, first + total):
+        if name == "paper32":
+            x0, y0, x1, y1 = centred_target(c["w"], c["h"], c["sw"], c["sh"])
+            shots.append(dict(w=c["w"], h=c["h"], x0=x0, y0=y0, x1=x1, y1=y1, p=None, count=c["count"],
+                              seed=c["seed"], shot=i))
+            continue
         if name == "mixed":
             side = c["sides"][int(uniform01(c["seed"], i, 0) * 4294967296.0) % len(c["sides"])]
             p = c["p_lo"] + (c["p_hi"] - c["p_lo"]) * uniform01(c["seed"], i, 1)
@@ -112,4 +135,6 @@ def config_shots(name: str, n: int | None = None, first: int = 0):
 
 def shot_grid(desc) -> np.ndarray:
     """Packed bit rows for one shot descriptor."""
+    if desc.get("count") is not None:
+        return pack_rows(fixed_count_grid(desc["seed"], desc["shot"], desc["w"], desc["h"], desc["count"]))
     return pack_rows(bernoulli_grid(desc["seed"], desc["shot"], desc["w"], desc["h"], desc["p"]))

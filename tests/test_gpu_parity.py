@@ -368,3 +368,25 @@ def test_ready_set_overflow_hands_over_to_general_path():
             r = oracle.solve(shapes[i], ri.shot_grid(shots[i]))
             rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF)
             same_batch(mb.host_batch(i, binf), rb, f"overflow neighbour {i} flags={flags}")
+
+
+def test_paper_geometry_many_and_single():
+    """The paper's benchmark geometry (32 x 54 traps, full-width 32 x 32 target, exactly 1036
+    atoms): 64 shots in one launch and 4 one at a time, solve and batching against the oracle."""
+    shots = ri.config_shots("paper32", n=64)
+    say("case paper32 many", len(shots))
+    mb, shapes, grids = run_many(shots)
+    sinf, binf = mb.solve_infos(), mb.batch_infos()
+    for i in range(len(shots)):
+        r = oracle.solve(shapes[i], grids[i])
+        same_solve(mb.host_solve(i, sinf), r, f"paper32 {i}")
+        rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"])
+        same_batch(mb.host_batch(i, binf), rb, f"paper32 batch {i}")
+    for i in range(4):
+        say("case paper32 single", i)
+        sb, g = gpu_solve(shapes[i], grids[i])
+        r = oracle.solve(shapes[i], grids[i])
+        same_solve(g, r, f"paper32 single {i}")
+        for flags in (0, 1, 2):
+            rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=flags)
+            same_batch(gpu_batch(sb, g["n_steps"], flags), rb, f"paper32 single {i} flags={flags}")
