@@ -247,10 +247,9 @@ def served_form(args, dev):
     arrivals = poisson_arrivals(args.serve_rate, args.serve_seconds, seed=50)
     order = np.arange(len(arrivals)) % len(pool)
     srv = Server(budget_bytes=args.serve_budget_gib << 30, max_wave=args.serve_max_wave, flags=args.flags)
-    warm = Server(budget_bytes=1 << 30, class_share={64: 0.5, 128: 0.5}, flags=args.flags)
-    for j in range(8):                               # first-launch costs outside the measurement
-        if max(shapes[j][0], shapes[j][1]) <= 128:
-            warm.submit(shapes[j], grids[j])
+    warm = Server(budget_bytes=2 << 30, class_share={64: 0.2, 128: 0.3, 256: 0.5}, flags=args.flags)
+    for j in range(16):                              # first-launch costs outside the measurement
+        warm.submit(shapes[j], grids[j])
     warm.drain()
     del warm
     wall = serve_stream(srv, shapes, grids, arrivals, order)
@@ -288,8 +287,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="served stream length (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-pool", type=int, default=1024)
-    ap.add_argument("--serve-budget-gib", type=int, default=48)
-    ap.add_argument("--serve-max-wave", type=int, default=256)
+    ap.add_argument("--serve-budget-gib", type=int, default=176)
+    ap.add_argument("--serve-max-wave", type=int, default=1024)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one plain device copy of this many MiB (a known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")

@@ -7,9 +7,11 @@ shot as soon as its class has a free slot: the number of slots per class is set 
 memory budget (admission by memory).  Every admitted group of shots becomes one *wave*: the
 wave's grids go to the device in one copy from pinned staging and are scattered into their slots,
 then one ``rr_solve_many`` + ``rr_batch_moves_many`` pair runs over just those slots.  Each class
-has several streams and waves take them in turn, so waves overlap on the device, and shots that
-arrive while others are on the GPU are admitted as slots free up.  A wave retires when its
-completion event has fired: its shots are stamped done and their slots return to the free list.
+has several streams and a wave is launched only on a stream of its class that is idle, so while
+the class's streams are busy, arrivals gather into the next, larger wave (a wave takes every
+waiting shot its free slots and ``max_wave`` allow); waves of all classes overlap on the device.
+A wave retires when its completion event has fired: its shots are stamped done and their slots
+return to the free list.
 
 Every result is that of a single ``rr_solve`` + ``rr_batch_moves`` on the same shot: the kernels
 work per instance and are deterministic, and a slot is sized so that the shot fits (a shot whose
@@ -32,9 +34,10 @@ from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuff
 
 
 def step_bound(side: int) -> int:
-    """Steps one slot of a class holds: about twice the mean step count of the configs' loadings
-    (~0.07 * side**3), never below 4096."""
-    return max(4096, int(0.15 * side ** 3))
+    """Steps one slot of a class holds: 0.11 * side**3, never below 4096.  The configs' loadings
+    take 0.067-0.069 * side**3 steps on average and at most 0.096 * side**3 (500 uneven shots,
+    sides 32..128, oracle); a shot beyond its slot is re-run alone."""
+    return max(4096, int(0.11 * side ** 3))
 
 
 class _Class:
@@ -58,7 +61,14 @@ class _Class:
         self.ws = torch.empty((n * self.ws_bytes + 7) // 8, dtype=torch.int64, device=device)
         self.free = collections.deque(range(n))
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
-        self.turn = 0
+        self.on_stream = [None] * n_streams          # the wave last launched on each stream
+
+    def idle_stream(self):
+        """Index of a stream whose last wave has finished (or that never ran one), else None."""
+        for j, w in enumerate(self.on_stream):
+            if w is None or w.event.query():
+                return j
+        return None
 
     @staticmethod
     def slot_bytes(side):
@@ -88,7 +98,7 @@ class Server:
         self.flags = int(flags)
         self.max_wave = int(max_wave)
         self.keep = bool(keep_results)
-        share = class_share or {64: 0.1, 128: 0.2, 256: 0.7}
+        share = class_share or {64: 0.04, 128: 0.12, 256: 0.84}
         self.classes = {}
         for side, f in share.items():
             n = int(budget_bytes * f) // _Class.slot_bytes(side)
@@ -122,13 +132,16 @@ class Server:
         for side, c in self.classes.items():
             q = self.waiting[side]
             while q and c.free:
+                j = c.idle_stream()
+                if j is None:
+                    break                              # the class's streams are busy: let the wave grow
                 k = min(len(q), len(c.free), self.max_wave)
-                self._launch(c, [q.popleft() for _ in range(k)], [c.free.popleft() for _ in range(k)])
+                self._launch(c, j, [q.popleft() for _ in range(k)], [c.free.popleft() for _ in range(k)])
                 launched += 1
         self._retire()
         return launched
 
-    def _launch(self, c, ids, slots):
+    def _launch(self, c, j, ids, slots):
         n = len(ids)
         d = np.zeros(n, DESC_DTYPE)
         stage = torch.zeros((n, c.occ_words), dtype=torch.int64, pin_memory=True)
@@ -150,8 +163,7 @@ class Server:
             sh["slot"] = s
         desc_h = torch.from_numpy(d.view(np.uint8).copy()).pin_memory()
         idx_h = torch.tensor(slots, dtype=torch.int64).pin_memory()
-        st = c.streams[c.turn % len(c.streams)]
-        c.turn += 1
+        st = c.streams[j]
         w = _Wave()
         with torch.cuda.stream(st):
             desc = desc_h.to(self.device, non_blocking=True)
@@ -168,6 +180,7 @@ class Server:
             w.event.record(st)
         w.cls, w.ids, w.slots, w.launched = c, ids, slots, time.perf_counter()
         w.keep_alive = (desc, idx, rows, desc_h, idx_h, stage)   # until the wave retires
+        c.on_stream[j] = w
         self.inflight.append(w)
         self.waves += 1
 
