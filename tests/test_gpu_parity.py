@@ -289,19 +289,24 @@ def test_device_planner_matches_host_plan_and_reports_overflow():
 
 
 def test_fast_path_equals_general_path_and_lds_budgets():
-    """The batching paths agree byte for byte: the fast path with its loop data in LDS, the fast
-    path with its loop data in the workspace (1 KiB LDS budget) and the general path, on uneven
-    sizes and the bench grid, for every constraint; the smaller grids also against the oracle."""
+    """The batching paths agree byte for byte, on uneven sizes and the bench grid, for every
+    constraint: the default launch (graph in LDS, or in LDS row tiles for grids beyond 64 KiB;
+    loop data in the workspace) against the general path, the loop data in LDS (64 KiB loop
+    budget), the graph in many small row tiles (12 KiB graph budget) and the graph in the
+    workspace (2 KiB: below one tile); the smaller grids also against the oracle."""
     shots = ri.config_shots("mixed", n=21) + ri.config_shots("batch64", n=6)
+    variants = {"general": GENERIC, "loop in LDS": 64 << 8, "graph in 12 KiB tiles": 12 << 24,
+                "graph in the workspace": 2 << 24}
     for flags in (0, 1, 2):
         say("case paths flags", flags)
         ref, shapes, grids = run_many(shots, flags)
-        gen, _, _ = run_many(shots, flags | GENERIC)
-        tiny, _, _ = run_many(shots, flags | (1 << 8))
         binf = ref.batch_infos()
+        for name, extra in variants.items():
+            say("  variant", name)
+            other, _, _ = run_many(shots, flags | extra)
+            for i in range(len(shots)):
+                same_batch(other.host_batch(i), ref.host_batch(i, binf), f"{name} {i} flags={flags}")
         for i in range(len(shots)):
-            same_batch(gen.host_batch(i), ref.host_batch(i, binf), f"general {i} flags={flags}")
-            same_batch(tiny.host_batch(i), ref.host_batch(i, binf), f"workspace {i} flags={flags}")
             if shapes[i][0] <= 64:
                 r = oracle.solve(shapes[i], grids[i])
                 if r["status"] == 0:
