@@ -38,7 +38,6 @@ constexpr uint32_t kMaxK = 65535;       // move indices fit 16 bits on the fast 
 constexpr int kMaxPreds = 8;            // distinct in-group predecessors of one move
 constexpr int kGT = 512;                // threads of the graph workgroup
 constexpr int kGWaves = kGT / kWave;
-constexpr int kMaxSlots = 8;            // largest register slot count of the loop kernel
 
 // release code of a move (16 bits): kind << 14 | next - b
 constexpr uint32_t kRelNone = 0, kRelNext = 1, kRelList = 2;
@@ -51,7 +50,7 @@ enum { ST_FAST = 0, ST_DONE = 1, ST_GENERIC = 2 };
 
 struct Layout {
     size_t hdr, mv, nx, gpend, gloff, hdoff, hd, gl, soff, sfill, slist, pend, preds, gbits, gcnt, hcnt, grp, cell,
-        touch, scratch, gen, total;
+        touch, gen, total;
     uint32_t Gc, GW;
     size_t GEc;
 };
@@ -95,9 +94,12 @@ __host__ __device__ inline Layout layout(int W, int H, uint32_t move_cap, uint32
     L.grp = take(2 * K);
     L.cell = take(4 * (WH + 1));
     L.touch = take(2 * OCC);
-    L.scratch = take(16 * (size_t)kWave * kMaxSlots);
-    L.gen = p;
-    L.total = p + al256(gen::ws_layout(W, H, move_cap, step_cap).total);
+    // the general path's region overlaps the fast path's arrays: it redoes an instance from its
+    // inputs, after the fast path has given it up, and needs nothing the fast path built; only
+    // the header (which holds the instance's state) stays apart
+    L.gen = L.mv;
+    const size_t gen_end = L.gen + al256(gen::ws_layout(W, H, move_cap, step_cap).total);
+    L.total = p > gen_end ? p : gen_end;
     return L;
 }
 
