@@ -145,7 +145,12 @@ struct GraphShared {
     uint32_t red[kGWaves];
     uint32_t flags;
     uint32_t nr;            // row ranges of the tiled build
+    uint32_t nlong;         // long horizontal legs of the current range, searched wave by wave
+    uint16_t longq[512];
 };
+
+constexpr int kLongLeg = 32;            // horizontal legs longer than this: one wave each
+constexpr uint32_t kLongCap = 512;
 
 __device__ __forceinline__ uint32_t add_wg32(uint32_t *p, uint32_t v)
 {
@@ -567,6 +572,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         uint16_t *touch = (uint16_t *)(tile + 4 * ((size_t)nc + 1));
         const uint32_t mlo = r ? roff[r - 1] : 0u, mhi = roff[r];
         for (uint32_t c = tid; c <= nc; c += kGT) cell[c] = 0;
+        if (tid == 0) S.nlong = 0;
         __syncthreads();
         for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
             int sx, sy, dx, dy;
@@ -585,26 +591,39 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         __syncthreads();
         // previous toucher of every visit in the range: the largest index below b on the
         // trap's list, read unsorted two entries at a time (the lists are short; a scan of
-        // independent reads beats sorting them and searching)
+        // independent reads beats sorting them and searching).  A thread per move -- except
+        // that a long horizontal leg (more than kLongLeg traps, in this range) is queued and
+        // searched afterwards by a whole wave, its lanes taking the leg's traps: one such leg
+        // in a wave of short walks would otherwise hold the other 63 lanes.
         const uint32_t *t32 = (const uint32_t *)touch;
+        auto prev_of = [&](uint32_t c, uint32_t b) -> uint32_t {   // previous toucher + 1, 0 if none
+            const uint32_t lo = c ? cell[c - 1] : 0u, hi = cell[c];
+            uint32_t best = 0;
+            for (uint32_t w = lo >> 1; w < (hi + 1) >> 1; ++w) {
+                const uint32_t v = t32[w], x0 = v & 0xFFFFu, x1 = v >> 16;
+                best = (2 * w >= lo && x0 < b && x0 >= best) ? x0 + 1 : best;
+                best = (2 * w + 1 < hi && x1 < b && x1 >= best) ? x1 + 1 : best;
+            }
+            return best;
+        };
         for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
             const uint32_t b = rlist[t];
             int sx, sy, dx, dy;
             load_move(I.moves, b, sx, sy, dx, dy);
             const uint32_t g = grp[b], glo = I.goff[g];     // b's group holds the moves glo..
+            bool defer = false;
+            if (sy >= y0 && sy < y1 && iabs(dx - sx) >= kLongLeg) {
+                const uint32_t at = add_wg32(&S.nlong, 1u);
+                if (at < kLongCap) { S.longq[at] = (uint16_t)b; defer = true; }
+            }
             uint32_t ps[kMaxPreds];
             int np = 0;
             bool loaded = false, changed = false, ovf = false;
             uint32_t last = 0xFFFFFFFFu, lastg = 0xFFFFFFFFu;
+            const int rowlo = sy * W;
             walk_rows(W, sx, sy, dx, dy, y0, y1, [&](int cg) {
-                const uint32_t c = (uint32_t)cg - c0;
-                const uint32_t lo = c ? cell[c - 1] : 0u, hi = cell[c];
-                uint32_t best = 0;              // previous toucher + 1, 0 when b is the first
-                for (uint32_t w = lo >> 1; w < (hi + 1) >> 1; ++w) {
-                    const uint32_t v = t32[w], x0 = v & 0xFFFFu, x1 = v >> 16;
-                    best = (2 * w >= lo && x0 < b && x0 >= best) ? x0 + 1 : best;
-                    best = (2 * w + 1 < hi && x1 < b && x1 >= best) ? x1 + 1 : best;
-                }
+                if (defer && (uint32_t)(cg - rowlo) < (uint32_t)W) return;  // the queued leg (corner included)
+                const uint32_t best = prev_of((uint32_t)cg - c0, b);
                 if (best == 0) return;
                 const uint32_t a = best - 1;
                 if (a == last) return;
@@ -636,6 +655,64 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
                     if (i < np) preds[(size_t)b * kMaxPreds + i] = (uint16_t)ps[i];
             }
             if (ovf) S.flags = 1;
+        }
+        __syncthreads();
+        // the queued long legs, one wave each
+        const uint32_t nq = S.nlong < kLongCap ? S.nlong : kLongCap;
+        for (uint32_t qi = (uint32_t)wid; qi < nq; qi += (uint32_t)kGWaves) {
+            const uint32_t b = S.longq[qi];
+            int sx, sy, dx, dy;
+            load_move(I.moves, b, sx, sy, dx, dy);
+            const uint32_t g = grp[b], glo = I.goff[g];
+            const int nh = iabs(dx - sx) + 1, sth = dx >= sx ? 1 : -1;
+            uint32_t ps[kMaxPreds];
+            int np = 0;
+            bool loaded = false, changed = false, ovf = false;
+            uint32_t lastg = 0xFFFFFFFFu;
+            for (int s0 = 0; s0 < nh; s0 += kWave) {
+                const int sv = s0 + lane;
+                uint32_t a = 0xFFFFFFFFu, ga = 0xFFFFFFFFu;
+                if (sv < nh) {
+                    const uint32_t best = prev_of((uint32_t)(sy * W + sx + sth * sv) - c0, b);
+                    if (best) {
+                        a = best - 1;
+                        if (a < glo) ga = grp[a];
+                    }
+                }
+                uint64_t act = ballot(a != 0xFFFFFFFFu);
+                while (act) {                   // the distinct previous touchers, one by one
+                    const int l = (int)__builtin_ctzll(act);
+                    const uint32_t u = (uint32_t)__builtin_amdgcn_readlane((int)a, l);
+                    act &= ~ballot(a == u);
+                    if (u >= glo) {
+                        if (!loaded) {
+                            np = (int)pend[b];
+#pragma unroll
+                            for (int i = 0; i < kMaxPreds; ++i)
+                                if (i < np) ps[i] = preds[(size_t)b * kMaxPreds + i];
+                            loaded = true;
+                        }
+                        const int before = np;
+                        set_add(ps, np, u, ovf);
+                        changed |= np != before;
+                    } else {
+                        const uint32_t gu = (uint32_t)__builtin_amdgcn_readlane((int)ga, l);
+                        if (gu != lastg) {
+                            lastg = gu;
+                            if (lane == 0)
+                                __hip_atomic_fetch_or(&gbits[g * GW + gu / 32], 1u << (gu & 31), __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                    }
+                }
+            }
+            if (changed && lane == 0) {
+                pend[b] = (uint32_t)np;
+#pragma unroll
+                for (int i = 0; i < kMaxPreds; ++i)
+                    if (i < np) preds[(size_t)b * kMaxPreds + i] = (uint16_t)ps[i];
+            }
+            if (ovf && lane == 0) S.flags = 1;
         }
         __syncthreads();
     }
