@@ -18,3 +18,13 @@ def wide_release(side=64, rows=(0, 16, 32, 48), width=60):
     n_steps = int((np.abs(mv[:, 2].astype(int) - mv[:, 0]) + np.abs(mv[:, 3].astype(int) - mv[:, 1])).sum())
     shape = (side, side, 0, 0, side, side)
     return shape, mv, np.asarray(group_off, np.uint32), n_steps
+
+
+def long_row(side=64, n=600, length=40, row=0):
+    """n moves, all along row `row` from column 0 to column `length` (one group).  Every trap
+    of the row's first length + 1 columns is on all n paths: the instance's touch lists
+    (n * (length + 1) entries) exceed a 64 KiB graph budget, so the tiled build takes it, and
+    the row's range holds n long horizontal legs -- more than the wave queue's 512."""
+    moves = [(0, row, length, row)] * n
+    mv = np.asarray(moves, np.uint16)
+    return (side, side, 0, 0, side, side), mv, np.asarray([0, n], np.uint32), n * length

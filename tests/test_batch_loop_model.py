@@ -96,3 +96,15 @@ def test_tiled_graph_equals_one_piece(tile_kib):
         most = max(most, R)
     if tile_kib < 60:
         assert most > 1
+
+
+def test_tiled_graph_long_row_fixture():
+    """The long-row fixture (600 identical 40-trap horizontal moves): the tiled build's
+    predecessor sets are the one-piece build's (each move waits on the one before it)."""
+    from crafted import long_row
+    shape, mv, goff, n_steps = long_row()
+    g = M.graph(shape, mv, goff)
+    preds, gbits, R = M.graph_tiled(shape, mv, goff, 60 * 1024)
+    assert R > 1 and gbits == {}
+    assert preds == [set()] + [{b - 1} for b in range(1, len(mv))]
+    assert [len(s) for s in g["succ"]] == [1] * (len(mv) - 1) + [0]

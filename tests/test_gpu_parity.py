@@ -395,3 +395,45 @@ def test_paper_geometry_many_and_single():
         for flags in (0, 1, 2):
             rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=flags)
             same_batch(gpu_batch(sb, g["n_steps"], flags), rb, f"paper32 single {i} flags={flags}")
+
+
+def test_tiled_graph_with_queue_overflow():
+    """A hand-made instance whose touch lists exceed the graph budget (tiled build) and whose
+    one row carries 600 long horizontal legs (more than the per-range wave queue holds): its
+    batches equal the oracle's in a many-instance launch and, with a 32 KiB graph budget, in a
+    one-instance launch."""
+    from crafted import long_row
+    from paper_2504_06182_amd.pipeline import SolveBuffers, ManyBuffers
+    shape, mv, goff, n_steps = long_row()
+    rb = oracle.batch(shape, mv, goff, n_steps)
+    say("case long row single")
+    sb = SolveBuffers(shape)
+    _load_crafted(sb, mv, goff, n_steps)
+    torch.cuda.synchronize()
+    same_batch(gpu_batch(sb, n_steps, 32 << 24), rb, "long row single")
+    say("case long row many")
+    shots = ri.config_shots("batch64", n=3)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    mb = ManyBuffers(shapes).load([ri.shot_grid(d) for d in shots]).solve()
+    torch.cuda.synchronize()
+    d1 = mb.desc_np[1]
+    mo, go = int(d1["move_off"]), int(d1["group_off"])
+    moves = mb.moves.cpu().numpy().copy()
+    moves[mo:mo + len(mv)] = np.ascontiguousarray(mv).reshape(-1).view(np.int64)
+    mb.moves.copy_(torch.from_numpy(moves).cuda())
+    groups = mb.groups.cpu().numpy().copy()
+    groups[go:go + len(goff)] = goff.view(np.int32)
+    mb.groups.copy_(torch.from_numpy(groups).cuda())
+    sinf = mb.solve_infos().copy()
+    sinf[1, :6] = (0, len(mv), len(goff) - 1, n_steps, len(mv), len(goff) - 1)
+    mb.sinfo.copy_(torch.from_numpy(sinf.reshape(-1).view(np.int32)).cuda())
+    torch.cuda.synchronize()
+    mb.plan_batches([max(int(i[3]), 1) for i in sinf])
+    mb.batch(0)
+    torch.cuda.synchronize()
+    binf = mb.batch_infos()
+    same_batch(mb.host_batch(1, binf), rb, "long row many")
+    for i in (0, 2):
+        r = oracle.solve(shapes[i], ri.shot_grid(shots[i]))
+        same_batch(mb.host_batch(i, binf), oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"]),
+                   f"long row neighbour {i}")
