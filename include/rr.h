@@ -74,7 +74,9 @@ typedef struct {
 #define RR_LAMBDA_ALONG       1u  /* same direction, on one line that runs along that direction */
 #define RR_LAMBDA_NONE        2u  /* only the vertex-disjointness of Alg. 3 */
 /* Run every instance on the general batching path (no ready-set register limit; slower).  The
- * default picks the fast path per instance and falls back to the general one by itself. */
+ * default picks the fast path per instance and falls back to the general one by itself: for
+ * instances beyond its limits, and for one whose ready set outgrows the loop kernel's
+ * registers while it runs (that instance is then redone from its inputs). */
 #define RR_BATCH_GENERIC      (1u << 16)
 
 /* Largest grid side the device kernels take. */
@@ -116,7 +118,11 @@ size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step
  *                    data of one instance, 0 = the library's default; bit 16: RR_BATCH_GENERIC;
  *                    bits 24..31: LDS budget in KiB for the dependency-graph build of one
  *                    instance, 0 = the library's default.  Bits 8..16 and 24..31 are tuning and
- *                    testing knobs: results do not depend on them.  Bits 17..23 must be 0.
+ *                    testing knobs: results do not depend on them.  The loop budget is raised
+ *                    to what the loop always keeps in LDS (8 B per group and 16 B per register
+ *                    position of the ready set: about 4 KiB for 64 x 64 grids); a graph budget
+ *                    too small for one row of traps builds the graph in the workspace.
+ *                    Bits 17..23 must be 0.
  *                    At most 2^20 - 1 moves in at most 1024 groups (always true for rr_solve
  *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.
  *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).
