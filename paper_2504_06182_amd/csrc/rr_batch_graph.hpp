@@ -149,6 +149,7 @@ struct GraphShared {
     uint16_t longq[512];
 };
 
+constexpr uint32_t kSortLo = 32;        // tiled build: lists longer than this (up to 128) are sorted
 constexpr int kLongLeg = 32;            // horizontal legs longer than this: one wave each
 constexpr uint32_t kLongCap = 512;
 
@@ -595,9 +596,52 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         // that a long horizontal leg (more than kLongLeg traps, in this range) is queued and
         // searched afterwards by a whole wave, its lanes taking the leg's traps: one such leg
         // in a wave of short walks would otherwise hold the other 63 lanes.
+        // Lists of kSortLo+1..128 entries (the receiver columns') are sorted first, a wave each
+        // (two entries per lane, bitonic network), and searched by bisection.
+        for (uint32_t cb = (uint32_t)wid * kWave; cb < nc; cb += (uint32_t)kGT) {
+            const uint32_t c = cb + lane;
+            uint32_t n = 0;
+            if (c < nc) n = cell[c] - (c ? cell[c - 1] : 0u);
+            uint64_t lm = ballot(n > kSortLo && n <= 2u * kWave);
+            while (lm) {
+                const int l = (int)__builtin_ctzll(lm);
+                lm &= lm - 1;
+                const uint32_t cl = cb + (uint32_t)l;
+                const uint32_t lo = cl ? cell[cl - 1] : 0u, n2 = cell[cl] - lo;
+                uint32_t ea = (uint32_t)lane < n2 ? touch[lo + lane] : 0xFFFFu;
+                uint32_t eb = (uint32_t)lane + kWave < n2 ? touch[lo + kWave + lane] : 0xFFFFu;
+                for (int k = 2; k <= 2 * kWave; k <<= 1) {
+                    for (int j = k >> 1; j > 0; j >>= 1) {
+                        if (j == kWave) {               // the two entries of a lane (k = 128)
+                            const uint32_t mn = ea < eb ? ea : eb, mx = ea < eb ? eb : ea;
+                            ea = mn; eb = mx;
+                        } else {
+                            const uint32_t xa = (uint32_t)__shfl_xor((int)ea, j, kWave);
+                            const uint32_t xb = (uint32_t)__shfl_xor((int)eb, j, kWave);
+                            const bool lower = (lane & j) == 0;
+                            const bool upa = (lane & k) == 0, upb = ((lane + kWave) & k) == 0;
+                            ea = (lower == upa) ? (ea < xa ? ea : xa) : (ea < xa ? xa : ea);
+                            eb = (lower == upb) ? (eb < xb ? eb : xb) : (eb < xb ? xb : eb);
+                        }
+                    }
+                }
+                if ((uint32_t)lane < n2) touch[lo + lane] = (uint16_t)ea;
+                if ((uint32_t)lane + kWave < n2) touch[lo + kWave + lane] = (uint16_t)eb;
+            }
+        }
+        __syncthreads();
         const uint32_t *t32 = (const uint32_t *)touch;
         auto prev_of = [&](uint32_t c, uint32_t b) -> uint32_t {   // previous toucher + 1, 0 if none
             const uint32_t lo = c ? cell[c - 1] : 0u, hi = cell[c];
+            if (hi - lo > kSortLo && hi - lo <= 2u * kWave) {     // sorted: the entry before b
+                if (touch[lo] >= b) return 0u;
+                uint32_t l = lo, h = hi;
+                while (h - l > 1) {
+                    const uint32_t mid = (l + h) >> 1;
+                    if (touch[mid] < b) l = mid; else h = mid;
+                }
+                return (uint32_t)touch[l] + 1u;
+            }
             uint32_t best = 0;
             for (uint32_t w = lo >> 1; w < (hi + 1) >> 1; ++w) {
                 const uint32_t v = t32[w], x0 = v & 0xFFFFu, x1 = v >> 16;
