@@ -64,6 +64,30 @@ def cpu_baseline(seconds: float, max_workers: int):
                       f"{len(ranges)} single-threaded oracle processes; 1-core latency {calib * 1e3:.2f} ms/shot"}
 
 
+def oracle_references(verify_shots: int, paper_shots: int, flags: int):
+    """Part of the CPU baseline leg, run before the GPU is touched: the oracle's solve and batching
+    results for the sampled shots of the 8192-shot workload and of the paper's geometry whose GPU
+    results the run checks bit for bit afterwards."""
+    import numpy as np
+
+    import oracle
+    import rr_inputs as ri
+    oracle.build()
+    refs = {}
+    for name, idx in ((WORKLOAD, np.linspace(0, 8191, verify_shots).astype(int) if verify_shots > 0 else []),
+                      ("paper32", range(min(8, paper_shots)))):
+        out = {}
+        for i in idx:
+            d = ri.config_shots(name, n=1, first=int(i))[0]
+            shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+            r = oracle.solve(shape, ri.shot_grid(d))
+            rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF) \
+                if r["status"] == 0 else None
+            out[int(i)] = (r, rb)
+        refs[name] = out
+    return refs
+
+
 BATCH_SOURCES = ("rr_batch.hip", "rr_batch_graph.hpp", "rr_batch_loop.hpp", "rr_batch_generic.hpp", "rr_device.hpp")
 PROFILE = os.path.join(ROOT, "profiles", "k_loop_many_batch64.md")
 
@@ -151,7 +175,7 @@ def mixed_graph_form(args, dev, replays):
 
 
 
-def paper_geometry_form(args, dev, n_single):
+def paper_geometry_form(args, dev, n_single, refs):
     """The paper's benchmark geometry (32 x 54 traps, full-width 32 x 32 target, exactly 1036 atoms
     per shot, 1000 shots): per-shot latency of one synchronised rr_solve launch -- the paper
     reports red-rec time per instance -- and of solve + batching, and the per-shot cost when all
@@ -159,7 +183,6 @@ def paper_geometry_form(args, dev, n_single):
     import numpy as np
     import torch
 
-    import oracle
     import rr_inputs as ri
     from paper_2504_06182_amd.pipeline import BatchBuffers, ManyBuffers, SolveBuffers
     from paper_2504_06182_amd.tune import flags_for
@@ -189,14 +212,14 @@ def paper_geometry_form(args, dev, n_single):
         bb.run(args.flags, stream)
         torch.cuda.synchronize()
         lat_b.append((time.perf_counter() - a) * 1e6)
-    exact = 0
-    for sb, bb, i in zip(sbs[:8], bbs[:8], range(8)):
-        g, r = sb.host(), oracle.solve(shapes[i], grids[i])
-        gb = bb.host()
-        rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=args.flags & 0xFF)
-        exact += int(g["status"] == r["status"] == 0 and np.array_equal(g["moves"], r["moves"])
-                     and np.array_equal(g["final"], r["final"]) and np.array_equal(gb["steps"], rb["steps"])
-                     and np.array_equal(gb["batch_off"], rb["batch_off"]))
+    exact = None
+    if refs:
+        exact = 0
+        for i, (r, rb) in refs.items():
+            g, gb = sbs[i].host(), bbs[i].host()
+            exact += int(g["status"] == r["status"] == 0 and np.array_equal(g["moves"], r["moves"])
+                         and np.array_equal(g["final"], r["final"]) and np.array_equal(gb["steps"], rb["steps"])
+                         and np.array_equal(gb["batch_off"], rb["batch_off"]))
 
     mb = ManyBuffers(shapes, device=dev).load(grids).solve(stream)
     torch.cuda.synchronize()
@@ -227,7 +250,7 @@ def paper_geometry_form(args, dev, n_single):
             "batched_solve_us_per_shot": round(ts * 1e3 / n, 3),
             "batched_solve_batch_us_per_shot": round((ts + tb) * 1e3 / n, 3),
             "batched_launch_ms": {"solve": round(ts, 3), "batch": round(tb, 3)},
-            "bit_exact_sample": f"{exact}/8",
+            "bit_exact_sample": f"{exact}/{len(refs)}" if refs else "not checked (--no-cpu)",
             "paper_context": {"red_rec_serial_cpu_us": 106, "red_rec_gpu_us": 197,
                               "hardware": "AMD Threadripper 2950X (CPU) / Nvidia Quadro RTX 4000 (GPU)",
                               "note": "mean time per instance over 1000 instances; batching not timed there"}}
@@ -299,9 +322,10 @@ def main():
               "(multi-GPU shot sharding is design-only); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)      # before the GPU is touched
+    cpu, refs = None, {}
+    if not args.no_cpu:                               # the CPU leg, before the GPU is touched
+        cpu = cpu_baseline(args.cpu_seconds, args.cpu_workers)
+        refs = oracle_references(args.verify_shots, args.paper_shots, args.flags)
 
     import numpy as np
     import torch
@@ -384,21 +408,17 @@ def main():
     bytes_solve = int((16 * ws_words + 8 * n_moves + 4 * (n_groups + 1) + 24 + 80).sum())
     bytes_batch = int((8 * n_moves + 4 * (n_groups + 1) + 24 + 80 + 4 * n_steps + 4 * (n_batches + 1) + 20).sum())
 
-    # bit-exact sample against the oracle
-    import oracle
-    oracle.build()
-    idx = np.linspace(0, n - 1, args.verify_shots).astype(int)
+    # bit-exact sample against the oracle's results computed in the CPU leg
+    ref64 = refs.get(WORKLOAD, {})
     mv = mb.moves.cpu().numpy(); gr = mb.groups.cpu().numpy().view(np.uint32); fi = mb.final.cpu().numpy()
     st = mb.steps.cpu().numpy().view(np.uint32); bo = mb.batches.cpu().numpy().view(np.uint32)
     exact = 0
-    for i in idx:
+    for i, (r, rb) in ref64.items():
         g = mb.host_solve(i, sinf, mv, gr, fi)
-        r = oracle.solve(shapes[i], grids[i])
         good = g["status"] == r["status"] and np.array_equal(g["final"], r["final"])
         if good and r["status"] == 0:
             good = np.array_equal(g["moves"], r["moves"]) and np.array_equal(g["group_off"], r["group_off"])
             gb = mb.host_batch(i, binf, st, bo)
-            rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], flags=args.flags & 0xFF)
             good = good and np.array_equal(gb["batch_off"], rb["batch_off"]) and np.array_equal(gb["steps"], rb["steps"])
         exact += int(good)
 
@@ -423,7 +443,7 @@ def main():
     per_launch_sps = len(per) / (tp1 - tp0)
     lat = np.array(lat)
 
-    paper = paper_geometry_form(args, dev, args.paper_shots) if args.paper_shots > 0 else None
+    paper = paper_geometry_form(args, dev, args.paper_shots, refs.get("paper32")) if args.paper_shots > 0 else None
     mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
     served = served_form(args, dev) if args.serve_seconds > 0 else None
 
@@ -468,7 +488,7 @@ def main():
         "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
                            "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),
                            "mean_batches": round(float(n_batches.mean()), 1)},
-        "bit_exact_sample": f"{exact}/{len(idx)}",
+        "bit_exact_sample": f"{exact}/{len(ref64)}" if ref64 else "not checked (--no-cpu)",
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
