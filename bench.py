@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--mixed-replays", type=int, default=3, help="graph replays of the uneven batch (0: skip)")
     ap.add_argument("--paper-shots", type=int, default=200,
                     help="shots of the paper's geometry timed one launch at a time (0: skip the form)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="served stream length (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="served stream length (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--serve-budget-gib", type=int, default=176)
