@@ -1,6 +1,8 @@
 """Lane-level CPU model of the fast batching path (the graph kernel and the register-resident
-loop kernel), written statement by statement after the HIP code: 64 lanes x S register slots,
-ballots as bit masks, the leader cache in scalars.  Test infrastructure: it lets the CPU suite
+loop kernel), written after the HIP code: 64 lanes x S register slots, ballots as bit masks, the
+leader cache in scalars.  Where the kernel does several lanes' work at once (the finished lanes'
+group count-downs, the lane-parallel convoy stores) the model does it lane by lane, which gives
+the same state.  Test infrastructure: it lets the CPU suite
 check the fast path's logic (leader runs, holes, in-place successors, compaction, the
 ready-set bound) against the oracle without a GPU; the GPU tests check the kernels themselves.
 """
