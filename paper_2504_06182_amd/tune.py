@@ -71,6 +71,29 @@ def flags_for(size_class: int, flags: int = 0, table: dict | None = None) -> int
     return flags | schedule_bits(e["graph_kib"], e["loop_kib"])
 
 
+def loop_lds_floor(side: int) -> int:
+    """Bytes the loop kernel always keeps in LDS for a class of largest grid side ``side`` (its
+    per-group counts and merge scratch: 8 B per group of at most 2 * side, 16 B per register
+    position); the library raises a smaller loop budget to this, so smaller candidates are the
+    same schedule."""
+    slots = 3 if side <= 64 else (5 if side <= 128 else 8)
+    return 8 * min(2 * side, 1024) + 16 * 64 * slots + 16
+
+
+def _distinct_loop_budgets(side: int, loop_kib):
+    """The loop budgets (KiB) that give distinct launches: of those at or below the floor, only
+    the smallest."""
+    floor = loop_lds_floor(side)
+    out, seen_floor = [], False
+    for k in sorted(int(v) for v in loop_kib):
+        if k * 1024 <= floor:
+            if seen_floor:
+                continue
+            seen_floor = True
+        out.append(k)
+    return out
+
+
 def _run(mb, flags, reps):
     """Batch every instance of ``mb`` ``reps`` times; the best graph and loop kernel times (ms)
     and the outputs of the last run."""
@@ -119,7 +142,9 @@ def tune_class(mb, constraint: int = 0, graph_kib=GRAPH_KIB, loop_kib=LOOP_KIB, 
         gt[int(g)] = t
     best_g = _pick(gt, DEFAULT_GRAPH_KIB)
     lt = {}
-    for lk in loop_kib:
+    side = max(max(s[0], s[1]) for s in mb.shapes)
+    side = 64 if side <= 64 else (128 if side <= 128 else 256)
+    for lk in _distinct_loop_budgets(side, loop_kib):
         _, t, out = _run(mb, constraint | schedule_bits(best_g, lk), reps)
         if not _same(out, ref):
             raise RuntimeError(f"loop budget {lk} KiB changed the batching outputs")

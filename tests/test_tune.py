@@ -55,3 +55,11 @@ def test_tuner_keeps_outputs_and_picks_a_candidate():
         assert e["graph_kib"] in (16, 64, 150) and e["loop_kib"] in (1, 24, 64)
         assert e["graph_ms"] > 0 and e["loop_ms"] > 0
         assert np.all(mb.batch_infos()[:, 0].view(np.int32) >= 0)
+
+
+def test_loop_budgets_below_the_floor_are_one_schedule():
+    # 64 class: 8*128 + 16*64*3 + 16 = 4112 B; 256 class: 8*512 + 16*64*8 + 16 = 12304 B
+    assert tune.loop_lds_floor(64) == 4112 and tune.loop_lds_floor(256) == 12304
+    assert tune._distinct_loop_budgets(64, (1, 4, 8, 16)) == [1, 8, 16]
+    assert tune._distinct_loop_budgets(256, (1, 4, 8, 16, 32)) == [1, 16, 32]
+
