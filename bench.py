@@ -6,9 +6,12 @@ rr_solve_many (red-rec on every shot) -> rr_plan_many (device-side arena layout 
 counts) -> rr_batch_moves_many (Alg. 3 on every shot), all on one stream with no host sync.
 Workload: 8192 shots of a 64x64 trap grid loaded i.i.d. Bernoulli(0.55), centred 44x44 target.
 
-Reported in one JSON line: batched shots/s (value), the 1-per-launch form (rr_solve +
-rr_batch_moves per shot) with p50/p99 latency, a bit-exact sample against the CPU oracle, the
-roofline of the dominant kernel, and the CPU oracle timed on the host cores.
+Reported in one JSON line: batched shots/s (value), the roofline of the dominant kernel, and
+the other forms of the same path: one shot per launch (rr_solve + rr_batch_moves) with p50/p99
+latency; the paper's own benchmark geometry, per launch and batched; the uneven-size batch as
+one graph-captured chain per size class; a served Poisson stream with continuous batching
+(p50/p99 overall and per class).  The CPU leg, run before the GPU is touched, times the oracle
+on the host cores and computes the oracle results the bit-exact samples are checked against.
 """
 from __future__ import annotations
 
