@@ -274,7 +274,7 @@ class ManyBuffers:
 # ------------------------------------------------------------------------------------------
 # uneven sizes: one launch chain per grid size class
 
-SIZE_CLASSES = (64, 128, 256)
+SIZE_CLASSES = (64, 128, 192, 256)
 
 
 def size_class(shape) -> int:

@@ -29,7 +29,7 @@ import torch
 
 from . import RR_E_CAPACITY, RR_OK, rr_batch_moves_many, rr_batch_workspace_bytes, rr_solve_many
 from .tune import flags_for
-from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuffers, SolveBuffers, size_class,
+from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuffers, SolveBuffers,
                        solve_caps, words_per_row)
 
 
@@ -110,6 +110,16 @@ class Server:
         self.overflow = 0
         self.waves = 0
 
+    def class_of(self, shape):
+        """The server's class for a shape: the smallest of its classes that holds the grid (the
+        server's classes are the keys of class_share; fewer classes than the launch-side size
+        classes keep fewer waves in flight on the GPU's four hardware queues)."""
+        side = max(int(shape[0]), int(shape[1]))
+        fit = [c for c in self.classes if c >= side]
+        if not fit:
+            raise ValueError(f"grid side {side} above every class of this server")
+        return min(fit)
+
     def slots(self):
         return {side: c.n for side, c in self.classes.items()}
 
@@ -117,7 +127,7 @@ class Server:
     def submit(self, shape, grid, t_arrive=None):
         """Queue one shot (shape (w, h, x0, y0, x1, y1), packed bit rows); returns its id."""
         shape = tuple(int(v) for v in shape)
-        side = size_class(shape)
+        side = self.class_of(shape)
         if side not in self.classes:
             raise ValueError(f"no slots for size class {side}")
         i = len(self.shots)
@@ -255,7 +265,7 @@ class Server:
 
     def latencies_us(self, side=None):
         return np.array([(s["t_done"] - s["t_arrive"]) * 1e6 for s in self.shots
-                         if s["t_done"] is not None and (side is None or size_class(s["shape"]) == side)])
+                         if s["t_done"] is not None and (side is None or self.class_of(s["shape"]) == side)])
 
 
 def poisson_arrivals(rate_hz: float, duration_s: float, seed: int) -> np.ndarray:

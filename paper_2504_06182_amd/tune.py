@@ -142,8 +142,8 @@ def tune_class(mb, constraint: int = 0, graph_kib=GRAPH_KIB, loop_kib=LOOP_KIB, 
         gt[int(g)] = t
     best_g = _pick(gt, DEFAULT_GRAPH_KIB)
     lt = {}
-    side = max(max(s[0], s[1]) for s in mb.shapes)
-    side = 64 if side <= 64 else (128 if side <= 128 else 256)
+    from .pipeline import size_class
+    side = max(size_class(s) for s in mb.shapes)
     for lk in _distinct_loop_budgets(side, loop_kib):
         _, t, out = _run(mb, constraint | schedule_bits(best_g, lk), reps)
         if not _same(out, ref):
