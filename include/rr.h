@@ -97,8 +97,14 @@ size_t rr_solve_workspace_bytes(rr_shape shape);
  *                    surplus with moves, one per receiver column in the order it was saturated.
  *   final_occ  [out] bit rows of the grid after all moves (H*ws words).
  *   info       [out] one rr_solve_info.
- * Infeasible instances (too few tokens, §II.B) give status RR_INFEASIBLE, zero moves and
- * final_occ = occ. */
+ * An instance is solved iff F = N - D - (x1-x0)*(y1-y0) >= 0, decided before any move: N is
+ * the number of tokens and D the number of target-row tokens beyond the target width,
+ * counted only when the target leaves side columns (the row pre-pass parks those tokens in
+ * the side columns and they never move again).  For a target spanning every column this is
+ * |S| >= |T| (§II.B); with side columns it is stricter, so an instance whose target is
+ * reachable can still be refused (a failure of the heuristic, e.g. a 4 x 4 grid whose row 1
+ * is full against the target [1,3) x [1,3)).  A refused instance gives status
+ * RR_INFEASIBLE, zero moves and final_occ = occ. */
 rr_status rr_solve(rr_shape shape, const uint64_t *occ,
                    rr_move *moves, uint32_t move_cap,
                    uint32_t *group_off, uint32_t group_cap,

@@ -237,3 +237,95 @@ def test_capacity_reporting():
     assert small["need_groups"] == len(full["group_off"]) - 1
     bad = oracle.solve((4, 4, 2, 2, 2, 3), np.zeros((4, 1), np.uint64))
     assert bad["rc"] == -1
+
+
+def reachable_by_token_moves(w, h, tmask):
+    """For every configuration of tokens on a w x h grid, whether unit moves of one token onto
+    an empty neighbouring trap can reach a configuration covering the target mask.  Moves are
+    reversible, so this is: the configuration's component of the configuration graph holds a
+    covering configuration (components by scipy on all 2^(w*h) configurations)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    n = w * h
+    states = np.arange(1 << n, dtype=np.int64)
+    rows, cols = [], []
+    for y in range(h):
+        for x in range(w):
+            c = y * w + x
+            for nb in ([c + 1] if x + 1 < w else []) + ([c + w] if y + 1 < h else []):
+                s = states[((states >> c) & 1) != ((states >> nb) & 1)]
+                rows.append(s)
+                cols.append(s ^ (1 << c) ^ (1 << nb))
+    r = np.concatenate(rows)
+    cc = np.concatenate(cols)
+    g = coo_matrix((np.ones(len(r), np.int8), (r, cc)), shape=(1 << n, 1 << n))
+    _, label = connected_components(g, directed=False)
+    good = np.zeros(label.max() + 1, bool)
+    good[label[(states & tmask) == tmask]] = True
+    return good[label]
+
+
+def target_mask(shape):
+    w = shape[0]
+    m = 0
+    for y in range(shape[3], shape[5]):
+        for x in range(shape[2], shape[4]):
+            m |= 1 << (y * w + x)
+    return m
+
+
+def parked_tokens(shape, dense):
+    """D: target-row tokens beyond the target width when side columns exist."""
+    w, h, x0, y0, x1, y1 = shape
+    if x0 == 0 and x1 == w:
+        return 0
+    return sum(max(0, int(dense[y].sum()) - (x1 - x0)) for y in range(y0, y1))
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 1, 1, 3, 3), (4, 4, 0, 1, 4, 3), (4, 4, 1, 0, 3, 4), (4, 4, 0, 0, 2, 2),
+                                   (4, 4, 2, 3, 3, 4), (4, 4, 1, 1, 4, 2), (4, 4, 0, 2, 4, 4)])
+def test_status_against_brute_force_reachability_4x4(shape):
+    """Every loading of a 4x4 grid: whenever the oracle solves an instance, a cover of the
+    target is reachable by unit token moves (brute force over all 2^16 configurations); an
+    unreachable instance is always refused; a reachable instance is refused only when target
+    rows hold tokens beyond the target width in side columns (they stay parked, so the rule
+    F = N - D - |T| >= 0 is stricter than |S| >= |T| there -- a failure of the heuristic, not of
+    the instance); on a full-width band the oracle solves exactly the reachable instances."""
+    w = h = 4
+    reach = reachable_by_token_moves(w, h, target_mask(shape))
+    full_width = shape[2] == 0 and shape[4] == w
+    for bits in range(1 << 16):
+        dense = np.array([(bits >> i) & 1 for i in range(16)], np.uint8).reshape(h, w)
+        st = oracle.solve(shape, pack_rows(dense))["status"]
+        if st == 0:
+            assert reach[bits]
+        elif reach[bits]:
+            assert not full_width and parked_tokens(shape, dense) > 0, bits
+        else:
+            assert st == 1
+
+
+def test_status_against_brute_force_reachability_3x3_every_target():
+    w = h = 3
+    for shape in all_rectangles(w, h):
+        reach = reachable_by_token_moves(w, h, target_mask(shape))
+        for bits in range(1 << 9):
+            dense = np.array([(bits >> i) & 1 for i in range(9)], np.uint8).reshape(h, w)
+            st = oracle.solve(shape, pack_rows(dense))["status"]
+            assert (st == 0) <= bool(reach[bits])
+            if reach[bits] and st != 0:
+                assert parked_tokens(shape, dense) > 0
+
+
+def test_parked_tokens_refuse_a_reachable_instance():
+    """The smallest kind of heuristic failure, worked by hand: 4x4 grid, row 1 full, target
+    [1,3) x [1,3) (4 traps).  The row pre-pass matches row 1's tokens at x = 1, 2 onto the target
+    and parks those at x = 0 and x = 3 (side columns, target row), so only 2 tokens count against
+    4 target traps: refused, though |S| = |T| = 4 and a cover is reachable (e.g. lift the row's
+    tokens at x = 0, 3 up one row and in one column)."""
+    shape = (4, 4, 1, 1, 3, 3)
+    dense = np.zeros((4, 4), np.uint8)
+    dense[1, :] = 1
+    r = oracle.solve(shape, pack_rows(dense))
+    assert r["status"] == 1 and len(r["moves"]) == 0
+    assert reachable_by_token_moves(4, 4, target_mask(shape))[int(sum(1 << (4 + x) for x in range(4)))]
