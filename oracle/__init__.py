@@ -67,6 +67,8 @@ def lib():
         L.rr_oracle_batch_moves.argtypes = [C.POINTER(Shape), P, P, C.POINTER(SolveInfo), C.c_uint32,
                                             P, C.c_uint32, P, C.c_uint32, C.POINTER(BatchInfo)]
         L.rr_oracle_batch_moves.restype = C.c_int
+        L.rr_oracle_batch_moves_indexed.argtypes = L.rr_oracle_batch_moves.argtypes
+        L.rr_oracle_batch_moves_indexed.restype = C.c_int
         L.rr_oracle_e1d_window.argtypes = [P, C.c_int, C.c_int, C.c_int]
         L.rr_oracle_e1d_window.restype = C.c_int
         L.rr_oracle_e1d_moves.argtypes = [P, C.c_int, C.c_int, C.c_int, P, P]
@@ -138,8 +140,12 @@ def solve(shape, occ, move_cap=None, group_cap=None, trace=False):
     return out
 
 
-def batch(shape, moves, group_off, n_steps, status=OK, flags=LAMBDA_LINE_OR_COL, batch_cap=None, step_cap=None):
-    """Run the oracle batching routine.  Returns rc, status, batch_off (uint32[nb+1]), steps."""
+def batch(shape, moves, group_off, n_steps, status=OK, flags=LAMBDA_LINE_OR_COL, batch_cap=None, step_cap=None,
+          indexed=False):
+    """Run the oracle batching routine.  Returns rc, status, batch_off (uint32[nb+1]), steps.
+
+    ``indexed`` selects the indexed form (reduced dependency graph, bucketed ready set), which
+    gives the same results as the literal form and is the one that can run large grids."""
     sh = make_shape(shape)
     moves = np.ascontiguousarray(moves, dtype=np.uint16).reshape(-1, 4)
     goff = np.ascontiguousarray(group_off, dtype=np.uint32)
@@ -151,9 +157,9 @@ def batch(shape, moves, group_off, n_steps, status=OK, flags=LAMBDA_LINE_OR_COL,
     boff = np.zeros(batch_cap + 1, np.uint32)
     steps = np.zeros(max(step_cap, 1), np.uint32)
     bi = BatchInfo()
-    rc = lib().rr_oracle_batch_moves(C.byref(sh), _ptr(moves) if len(moves) else None,
-                                     _ptr(goff), C.byref(si), flags, _ptr(boff), batch_cap,
-                                     _ptr(steps), step_cap, C.byref(bi))
+    fn = lib().rr_oracle_batch_moves_indexed if indexed else lib().rr_oracle_batch_moves
+    rc = fn(C.byref(sh), _ptr(moves) if len(moves) else None, _ptr(goff), C.byref(si), flags, _ptr(boff),
+            batch_cap, _ptr(steps), step_cap, C.byref(bi))
     out = dict(rc=rc, status=bi.status, need_batches=bi.need_batches, need_steps=bi.need_steps)
     if rc == 0 and bi.status == OK:
         out["batch_off"] = boff[:bi.n_batches + 1].copy()

@@ -13,7 +13,9 @@
  * Pins (tests/): exact-1D window against brute-force assignment and the quadratic worst case of
  * §III.A; every solve replayed move by move (source occupied, path free, one token per trap,
  * Manhattan length, target covered iff status OK, feasibility formula); the pair loop against
- * hand-worked fixtures; batches replayed step by step against the solve's final grid.
+ * hand-worked fixtures and a naive re-implementation of the pairing rule; batches replayed
+ * step by step against the solve's final grid; the indexed batching form equal to the literal
+ * one on fixtures and random instances.
  * Parity unpinned: the tie-break conventions (leftmost E1D window, Stage-H centring offset,
  * pair-key tie order, receiver split tie, co-location order, constraint reading) are readings,
  * not results the paper fixes; they are pinned only by the hand-worked fixtures.
@@ -760,5 +762,267 @@ done:
     if (gpred) for (uint32_t g = 0; g < G; ++g) free(gpred[g].a);
     free(grp); free(len); free(pos); free(alive); free(indeg); free(succ); free(gbits); free(gpred);
     free(gremain); free(unlocked); free(stamp); free(Q); free(B); free(outb.a); free(outs.a);
+    return rc;
+}
+
+/* ---------------------------------------------------------------------------------------- */
+/* Batching, indexed form: the same Alg. 3 for instances far beyond what the literal form    */
+/* above can run (a 1024 x 1024 shot has ~6e5 moves and ~1e8 unit steps).                  */
+/*                                                                                          */
+/* Semantics are those of rr_oracle_batch_moves; only the bookkeeping differs:              */
+/*  - Gamma is kept reduced.  A move waits on the previous toucher of each trap of its path */
+/*    within its group, and a group on the previous group touching each of its traps.  The  */
+/*    full relation follows by transitivity: the touchers of one trap are chained in index  */
+/*    (group) order, so the last one having finished (completed) implies every earlier one  */
+/*    has, and readiness is unchanged.                                                      */
+/*  - The ready moves are kept in ascending index, and bucketed by (direction of the next   */
+/*    step, row) and (direction, column) of their current trap.  Each iteration's Q is the  */
+/*    ready set at its start (all updates wait until the batch is formed).  The first move  */
+/*    of Q always enters the batch; under the line-or-column constraint every other step    */
+/*    that could join it moves the same way on the first one's row or column, and once a   */
+/*    second step has joined, the line it shares with the first is the only one left (a     */
+/*    step compatible with both members yet off that line would stand on the first one's    */
+/*    trap), so scanning the two buckets in index order visits exactly the candidates the   */
+/*    literal scan of Q would accept.  Under "along" the one bucket of the motion's line is */
+/*    scanned; without constraint the whole of Q.  Trap disjointness is tested as stated.   */
+/* The two forms are checked equal on fixtures and random instances by the tests.           */
+
+typedef struct { uint32_t *a; uint32_t n, cap; } sarr;     /* ascending move indices */
+
+static int sa_find(const sarr *s, uint32_t v)
+{
+    uint32_t lo = 0, hi = s->n;
+    while (lo < hi) { uint32_t m = (lo + hi) / 2; if (s->a[m] < v) lo = m + 1; else hi = m; }
+    return (int)lo;
+}
+
+static int sa_insert(sarr *s, uint32_t v)
+{
+    if (s->n == s->cap) {
+        uint32_t nc = s->cap ? 2 * s->cap : 8;
+        uint32_t *na = (uint32_t *)realloc(s->a, nc * sizeof(uint32_t));
+        if (!na) return 0;
+        s->a = na; s->cap = nc;
+    }
+    int k = sa_find(s, v);
+    memmove(s->a + k + 1, s->a + k, (s->n - (uint32_t)k) * sizeof(uint32_t));
+    s->a[k] = v; s->n++;
+    return 1;
+}
+
+static void sa_remove(sarr *s, uint32_t v)
+{
+    int k = sa_find(s, v);
+    if ((uint32_t)k < s->n && s->a[k] == v) {
+        memmove(s->a + k, s->a + k + 1, (s->n - (uint32_t)k - 1) * sizeof(uint32_t));
+        s->n--;
+    }
+}
+
+typedef struct {
+    const o_move *mv;
+    int W, H;
+    int *pos, *len;
+    uint8_t *rdir; uint16_t *rx, *ry;      /* bucket keys of a ready move */
+    sarr ready, *rowb, *colb;              /* rowb[dir*H + y], colb[dir*W + x] */
+    int oom;
+} ix_state;
+
+static void ix_step(const ix_state *X, uint32_t b, o_step *e)
+{
+    path_cell(&X->mv[b], X->pos[b], &e->ux, &e->uy);
+    path_cell(&X->mv[b], X->pos[b] + 1, &e->vx, &e->vy);
+    e->dir = step_dir(e->ux, e->uy, e->vx, e->vy);
+}
+
+static void ix_make_ready(ix_state *X, uint32_t b)
+{
+    o_step e;
+    ix_step(X, b, &e);
+    X->rdir[b] = (uint8_t)e.dir; X->rx[b] = (uint16_t)e.ux; X->ry[b] = (uint16_t)e.uy;
+    if (!sa_insert(&X->ready, b) || !sa_insert(&X->rowb[e.dir * X->H + e.uy], b) ||
+        !sa_insert(&X->colb[e.dir * X->W + e.ux], b))
+        X->oom = 1;
+}
+
+static void ix_unready(ix_state *X, uint32_t b)
+{
+    sa_remove(&X->ready, b);
+    sa_remove(&X->rowb[X->rdir[b] * X->H + X->ry[b]], b);
+    sa_remove(&X->colb[X->rdir[b] * X->W + X->rx[b]], b);
+}
+
+int rr_oracle_batch_moves_indexed(const o_shape *shape, const o_move *mv, const uint32_t *goff,
+                                  const o_solve_info *si, uint32_t flags, uint32_t *batch_off, uint32_t batch_cap,
+                                  uint32_t *steps, uint32_t step_cap, o_batch_info *bi)
+{
+    if (!shape_ok(shape) || !si || !bi || flags > O_LAMBDA_NONE) return O_E_INVAL;
+    memset(bi, 0, sizeof *bi);
+    const int W = shape->w, H = shape->h;
+    if (si->status == O_INFEASIBLE || (si->status == O_OK && si->n_moves == 0)) {
+        bi->status = O_OK;
+        if (batch_off) batch_off[0] = 0;
+        return O_OK;
+    }
+    if (si->status != O_OK || !mv || !goff) { bi->status = O_E_INVAL; return O_OK; }
+    const uint32_t K = si->n_moves, G = si->n_groups;
+    if (goff[0] != 0 || goff[G] != K) { bi->status = O_E_INVAL; return O_OK; }
+    for (uint32_t g = 0; g < G; ++g) if (goff[g] > goff[g + 1]) { bi->status = O_E_INVAL; return O_OK; }
+    for (uint32_t b = 0; b < K; ++b)
+        if (mv[b].sx >= W || mv[b].dx >= W || mv[b].sy >= H || mv[b].dy >= H || path_len(&mv[b]) == 0) {
+            bi->status = O_E_INVAL; return O_OK;
+        }
+    uint64_t T = 0;
+    for (uint32_t b = 0; b < K; ++b) T += (uint64_t)path_len(&mv[b]);
+    if (T > step_cap) {
+        bi->status = O_E_CAPACITY; bi->need_steps = (uint32_t)T; bi->need_batches = (uint32_t)T;
+        return O_OK;
+    }
+
+    const uint32_t NONE = 0xFFFFFFFFu;
+    size_t WH = (size_t)W * H;
+    int rc = O_OK;
+    ix_state X;
+    memset(&X, 0, sizeof X);
+    X.mv = mv; X.W = W; X.H = H;
+    uint32_t *grp = (uint32_t *)malloc(sizeof(uint32_t) * K);
+    X.len = (int *)malloc(sizeof(int) * K);
+    X.pos = (int *)calloc(K, sizeof(int));
+    X.rdir = (uint8_t *)calloc(K, 1);
+    X.rx = (uint16_t *)calloc(K, sizeof(uint16_t));
+    X.ry = (uint16_t *)calloc(K, sizeof(uint16_t));
+    X.rowb = (sarr *)calloc((size_t)4 * H, sizeof(sarr));
+    X.colb = (sarr *)calloc((size_t)4 * W, sizeof(sarr));
+    uint32_t *last = (uint32_t *)malloc(sizeof(uint32_t) * WH);      /* last toucher of a trap */
+    uint32_t *lastg = (uint32_t *)malloc(sizeof(uint32_t) * WH);     /* its group */
+    uint32_t *seen = (uint32_t *)calloc(K, sizeof(uint32_t));
+    uint32_t *gseen = (uint32_t *)calloc(G + 1, sizeof(uint32_t));
+    int *indeg = (int *)calloc(K, sizeof(int));
+    int *gwait = (int *)calloc(G + 1, sizeof(int));
+    int *gremain = (int *)calloc(G + 1, sizeof(int));
+    u32vec *succ = (u32vec *)calloc(K, sizeof(u32vec));
+    u32vec *gsucc = (u32vec *)calloc(G + 1, sizeof(u32vec));
+    uint32_t *stamp = (uint32_t *)calloc(WH, sizeof(uint32_t));
+    uint32_t *acc = (uint32_t *)malloc(sizeof(uint32_t) * K);
+    if (!grp || !X.len || !X.pos || !X.rdir || !X.rx || !X.ry || !X.rowb || !X.colb || !last || !lastg || !seen ||
+        !gseen || !indeg || !gwait || !gremain || !succ || !gsucc || !stamp || !acc) { rc = O_E_NOMEM; goto done; }
+
+    for (uint32_t g = 0; g < G; ++g)
+        for (uint32_t b = goff[g]; b < goff[g + 1]; ++b) { grp[b] = g; gremain[g]++; }
+    for (uint32_t b = 0; b < K; ++b) X.len[b] = path_len(&mv[b]);
+    for (size_t c = 0; c < WH; ++c) { last[c] = NONE; lastg[c] = NONE; }
+
+    /* reduced Gamma, groups and moves in order */
+    for (uint32_t g = 0; g < G; ++g)
+        for (uint32_t b = goff[g]; b < goff[g + 1]; ++b)
+            for (int s = 0; s <= X.len[b]; ++s) {
+                int x, y; path_cell(&mv[b], s, &x, &y);
+                size_t c = (size_t)y * W + x;
+                uint32_t pg = lastg[c];
+                if (pg == g) {
+                    uint32_t a = last[c];
+                    if (seen[a] != b + 1) { seen[a] = b + 1; uv_push(&succ[a], b); indeg[b]++; }
+                } else if (pg != NONE && gseen[pg] != g + 1) {
+                    gseen[pg] = g + 1; uv_push(&gsucc[pg], g); gwait[g]++;
+                }
+                last[c] = b; lastg[c] = g;
+            }
+    for (uint32_t b = 0; b < K; ++b) if (succ[b].oom) { rc = O_E_NOMEM; goto done; }
+    for (uint32_t g = 0; g < G; ++g) if (gsucc[g].oom) { rc = O_E_NOMEM; goto done; }
+
+    for (uint32_t b = 0; b < K; ++b)
+        if (indeg[b] == 0 && gwait[grp[b]] == 0) ix_make_ready(&X, b);
+
+    uint64_t n_alive = K, n_out = 0, nb = 0;
+    uint32_t iter = 0;
+    if (batch_off) batch_off[0] = 0;
+    while (n_alive > 0 && !X.oom) {
+        if (X.ready.n == 0) { bi->status = O_E_INTERNAL; goto done; }
+        ++iter;
+        uint32_t na = 0;
+        o_step e;
+        /* the first move of Q always joins */
+        uint32_t lead = X.ready.a[0];
+        o_step L;
+        ix_step(&X, lead, &L);
+        acc[na++] = lead;
+        stamp[(size_t)L.uy * W + L.ux] = iter;
+        stamp[(size_t)L.vy * W + L.vx] = iter;
+        if (flags == O_LAMBDA_NONE) {
+            for (uint32_t q = 1; q < X.ready.n; ++q) {
+                uint32_t b = X.ready.a[q];
+                ix_step(&X, b, &e);
+                if (stamp[(size_t)e.uy * W + e.ux] == iter || stamp[(size_t)e.vy * W + e.vx] == iter) continue;
+                acc[na++] = b;
+                stamp[(size_t)e.uy * W + e.ux] = iter;
+                stamp[(size_t)e.vy * W + e.vx] = iter;
+            }
+        } else {
+            const sarr *rb = &X.rowb[L.dir * H + L.uy], *cb = &X.colb[L.dir * W + L.ux];
+            int use_row = 1, use_col = 1;
+            if (flags == O_LAMBDA_ALONG) { if (L.dir >= 2) use_row = 0; else use_col = 0; }
+            uint32_t ir = 0, ic = 0;
+            for (;;) {
+                uint32_t br = (use_row && ir < rb->n) ? rb->a[ir] : NONE;
+                uint32_t bc = (use_col && ic < cb->n) ? cb->a[ic] : NONE;
+                if (br == NONE && bc == NONE) break;
+                int from_row = br < bc;
+                uint32_t b = from_row ? br : bc;
+                if (from_row) ir++; else ic++;
+                if (b == lead) continue;
+                ix_step(&X, b, &e);
+                if (stamp[(size_t)e.uy * W + e.ux] == iter || stamp[(size_t)e.vy * W + e.vx] == iter) continue;
+                acc[na++] = b;
+                stamp[(size_t)e.uy * W + e.ux] = iter;
+                stamp[(size_t)e.vy * W + e.vx] = iter;
+                if (flags == O_LAMBDA_LINE_OR_COL && na == 2) {      /* the line is fixed */
+                    if (from_row) use_col = 0; else use_row = 0;
+                }
+            }
+        }
+        /* emit the batch in acceptance order, then advance, finish and release */
+        for (uint32_t k = 0; k < na; ++k) {
+            ix_step(&X, acc[k], &e);
+            if (steps) steps[n_out] = ((uint32_t)e.dir << 30) | ((uint32_t)e.ux << 15) | (uint32_t)e.uy;
+            n_out++;
+        }
+        ++nb;
+        if (batch_off && nb <= batch_cap) batch_off[nb] = (uint32_t)n_out;
+        for (uint32_t k = 0; k < na; ++k) {
+            uint32_t b = acc[k];
+            ix_unready(&X, b);
+            X.pos[b]++;
+            if (X.pos[b] < X.len[b]) { ix_make_ready(&X, b); continue; }
+            n_alive--;
+            for (size_t s = 0; s < succ[b].n; ++s) {
+                uint32_t t = succ[b].a[s];
+                if (--indeg[t] == 0 && gwait[grp[t]] == 0) ix_make_ready(&X, t);
+            }
+            uint32_t g = grp[b];
+            if (--gremain[g] == 0)
+                for (size_t s = 0; s < gsucc[g].n; ++s) {
+                    uint32_t h = gsucc[g].a[s];
+                    if (--gwait[h] == 0)
+                        for (uint32_t m = goff[h]; m < goff[h + 1]; ++m)
+                            if (indeg[m] == 0 && X.pos[m] < X.len[m]) ix_make_ready(&X, m);
+                }
+        }
+    }
+    if (X.oom) { rc = O_E_NOMEM; goto done; }
+    bi->need_batches = (uint32_t)nb;
+    bi->need_steps = (uint32_t)n_out;
+    if (nb > batch_cap || !batch_off || (n_out && !steps)) { bi->status = O_E_CAPACITY; goto done; }
+    bi->status = O_OK;
+    bi->n_batches = (uint32_t)nb;
+    bi->n_steps = (uint32_t)n_out;
+done:
+    if (succ) for (uint32_t b = 0; b < K; ++b) free(succ[b].a);
+    if (gsucc) for (uint32_t g = 0; g <= G; ++g) free(gsucc[g].a);
+    if (X.rowb) for (int k = 0; k < 4 * H; ++k) free(X.rowb[k].a);
+    if (X.colb) for (int k = 0; k < 4 * W; ++k) free(X.colb[k].a);
+    free(X.ready.a);
+    free(grp); free(X.len); free(X.pos); free(X.rdir); free(X.rx); free(X.ry); free(X.rowb); free(X.colb);
+    free(last); free(lastg); free(seen); free(gseen); free(indeg); free(gwait); free(gremain); free(succ);
+    free(gsucc); free(stamp); free(acc);
     return rc;
 }

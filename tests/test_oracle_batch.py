@@ -121,3 +121,77 @@ def test_capacity_reporting():
     assert small["status"] == -2
     assert small["need_batches"] == len(full["batch_off"]) - 1
     assert small["need_steps"] == r["n_steps"]
+
+
+# ---- the indexed form (reduced dependency graph, bucketed ready set) against the literal form
+
+def _both(shape, r, flags):
+    a = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], status=r["status"], flags=flags)
+    b = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], status=r["status"], flags=flags, indexed=True)
+    return a, b
+
+
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.json"))))
+def test_indexed_equals_literal_on_fixtures(path):
+    g = json.load(open(path))
+    shape = tuple(g["shape"])
+    occ = pack_rows(dense_from_tokens(shape[0], shape[1], g["tokens"]))
+    r = oracle.solve(shape, occ)
+    for flags in (0, 1, 2):
+        a, b = _both(shape, r, flags)
+        assert a["status"] == b["status"] == 0
+        assert np.array_equal(a["batch_off"], b["batch_off"]) and np.array_equal(a["steps"], b["steps"])
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2])
+def test_indexed_equals_literal_random(flags):
+    """Random grids up to 64 x 64 (full-width and side-column targets), every constraint:
+    batch ends and steps identical, byte for byte."""
+    rng = random.Random(77 + flags)
+    n = 0
+    for i in range(300):
+        w, h = rng.randint(1, 64), rng.randint(1, 64)
+        if rng.random() < 0.3:
+            x0, x1 = 0, w
+        else:
+            sw = rng.randint(1, w); x0 = rng.randint(0, w - sw); x1 = x0 + sw
+        sh = rng.randint(1, h); y0 = rng.randint(0, h - sh)
+        shape = (w, h, x0, y0, x1, y0 + sh)
+        occ = pack_rows(bernoulli_grid(500, i, w, h, rng.uniform(0.45, 0.95)))
+        r = oracle.solve(shape, occ)
+        if r["status"] != 0:
+            continue
+        a, b = _both(shape, r, flags)
+        assert a["status"] == b["status"] == 0, (i, shape)
+        assert np.array_equal(a["batch_off"], b["batch_off"]), (i, shape)
+        assert np.array_equal(a["steps"], b["steps"]), (i, shape)
+        n += 1
+    assert n >= 200
+
+
+@pytest.mark.parametrize("name", ["single32", "batch64", "single128", "mixed"])
+def test_indexed_equals_literal_workloads(name):
+    for d in config_shots(name, n=2):
+        if d["w"] > 128:
+            continue
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        r = oracle.solve(shape, shot_grid(d))
+        for flags in (0, 1, 2):
+            a, b = _both(shape, r, flags)
+            assert np.array_equal(a["batch_off"], b["batch_off"]) and np.array_equal(a["steps"], b["steps"])
+
+
+def test_indexed_capacity_and_invalid_like_literal():
+    d = config_shots("single32")[0]
+    shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+    r = oracle.solve(shape, shot_grid(d))
+    full = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], indexed=True)
+    for kw in (dict(batch_cap=3), dict(step_cap=10)):
+        a = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], **kw)
+        b = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], indexed=True, **kw)
+        assert a["status"] == b["status"] == -2
+        assert (a["need_batches"], a["need_steps"]) == (b["need_batches"], b["need_steps"])
+    assert full["status"] == 0
+    bad = np.array(r["moves"]).copy()
+    bad[0, 2] = bad[0, 0]; bad[0, 3] = bad[0, 1]           # zero-length move
+    assert oracle.batch(shape, bad, r["group_off"], r["n_steps"], indexed=True)["status"] == -1
