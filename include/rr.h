@@ -157,8 +157,9 @@ rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const uint32_t *g
  *   group_off  uint32 elements (group_cap + 1 of them)
  *   step_off   uint32 elements (step_cap of them)           -- rr_batch_moves_many only
  *   batch_off  uint32 elements (batch_cap + 1 of them)      -- rr_batch_moves_many only
- *   ws_off     bytes into the batching workspace, at least
- *              rr_batch_workspace_bytes(shape, move_cap, step_cap) apart -- rr_batch_moves_many */
+ *   ws_off     bytes into the batching workspace, a multiple of 256, the instance's region of
+ *              rr_batch_workspace_bytes(shape, move_cap, step_cap) bytes inside the workspace
+ *              and shared with no other instance -- rr_batch_moves_many only */
 typedef struct {
     rr_shape shape;
     uint16_t pad0, pad1;
@@ -175,7 +176,11 @@ rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_
                         uint64_t *final_arena, rr_solve_info *infos, void *stream);
 
 /* Batch the moves of n solved instances in one launch (same semantics and flags as
- * rr_batch_moves; the LDS budget in flags bits 8..15 applies to every instance). */
+ * rr_batch_moves; the LDS budget in flags bits 8..15 applies to every instance).
+ * workspace_bytes is the size of `workspace`: an instance whose region (ws_off and
+ * rr_batch_workspace_bytes of its shape and capacities) is misaligned or runs past it gets
+ * status RR_E_INVAL in binfos[i], and nothing of that instance is written, workspace
+ * included. */
 rr_status rr_batch_moves_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
                               const rr_move *move_arena, const uint32_t *group_arena,
                               const rr_solve_info *sinfos, uint32_t flags,

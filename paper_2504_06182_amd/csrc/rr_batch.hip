@@ -27,13 +27,25 @@ namespace rr {
 
 constexpr uint32_t kFlagGeneric = 1u << 16;
 
-// shape check of a many-instance descriptor; false also when the planner found no room
-__device__ __forceinline__ bool desc_usable(const rr_desc &d, int maxw, int maxh)
+// shape check of a many-instance descriptor
+__device__ __forceinline__ bool shape_usable(const rr_shape s, int maxw, int maxh)
 {
-    const rr_shape s = d.shape;
-    const bool ok = s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= RR_MAX_SIDE && s.h <= RR_MAX_SIDE &&
-                    s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
-    return ok && d.step_cap != 0xFFFFFFFFu;
+    return s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= RR_MAX_SIDE && s.h <= RR_MAX_SIDE &&
+           s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
+}
+
+// the instance's workspace region [ws_off, ws_off + layout total) is 256-byte aligned and lies
+// inside the workspace
+__device__ __forceinline__ bool ws_fits(const rr_desc &d, uint64_t ws_bytes)
+{
+    const uint64_t need = fast::layout(d.shape.w, d.shape.h, d.move_cap, d.step_cap).total;
+    return (d.ws_off & 255u) == 0 && d.ws_off <= ws_bytes && need <= ws_bytes - d.ws_off;
+}
+
+// a descriptor the kernels may run: valid shape, room found by the planner, workspace in bounds
+__device__ __forceinline__ bool desc_usable(const rr_desc &d, int maxw, int maxh, uint64_t ws_bytes)
+{
+    return shape_usable(d.shape, maxw, maxh) && d.step_cap != 0xFFFFFFFFu && ws_fits(d, ws_bytes);
 }
 
 __device__ __forceinline__ fast::Inst inst_of(const rr_desc &d, uint32_t i, const rr_move *mv, const uint32_t *ga,
@@ -68,19 +80,18 @@ __global__ __launch_bounds__(fast::kGT) void k_graph_one(fast::Inst I, uint32_t 
 __global__ __launch_bounds__(fast::kGT) void k_graph_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                           const rr_move *mv, const uint32_t *ga,
                                                           const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
-                                                          rr_batch_info *binfos, uint8_t *ws, uint32_t lds_bytes,
-                                                          uint32_t flags)
+                                                          rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,
+                                                          uint32_t lds_bytes, uint32_t flags)
 {
     __shared__ fast::GraphShared S;
     const uint32_t i = blockIdx.x;
     const rr_desc d = desc[i];
-    if (!desc_usable(d, maxw, maxh)) {
+    if (!desc_usable(d, maxw, maxh, ws_bytes)) {
         if (threadIdx.x == 0) {
-            const rr_shape s = d.shape;
-            const bool shape_ok = s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= RR_MAX_SIDE &&
-                                  s.h <= RR_MAX_SIDE && s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
             const rr_solve_info si = sinfos[i];
-            if (!shape_ok)
+            // a workspace region out of bounds is a malformed descriptor (the planner never
+            // gives one to an instance it found room for)
+            if (!shape_usable(d.shape, maxw, maxh) || (d.step_cap != 0xFFFFFFFFu && !ws_fits(d, ws_bytes)))
                 fast::put_info(binfos + i, RR_E_INVAL, 0, 0, 0, 0);
             else if (si.status == RR_INFEASIBLE || (si.status == RR_OK && si.n_moves == 0))
                 fast::put_info(binfos + i, RR_OK, 0, 0, 0, 0);   // nothing to batch (no room needed)
@@ -118,11 +129,12 @@ template <int S, uint32_t F>
 __global__ __launch_bounds__(kWave) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                      const rr_move *mv, const uint32_t *ga,
                                                      const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
-                                                     rr_batch_info *binfos, uint8_t *ws, uint32_t lds_bytes)
+                                                     rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,
+                                                     uint32_t lds_bytes)
 {
     const uint32_t i = blockIdx.x;
     const rr_desc d = desc[i];
-    if (!desc_usable(d, maxw, maxh)) return;
+    if (!desc_usable(d, maxw, maxh, ws_bytes)) return;
     loop_entry<S, F>(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), lds_bytes);
 }
 
@@ -153,13 +165,13 @@ __global__ __launch_bounds__(kWave) void k_generic_one(fast::Inst I, uint32_t ld
 __global__ __launch_bounds__(kWave) void k_generic_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                         const rr_move *mv, const uint32_t *ga,
                                                         const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
-                                                        rr_batch_info *binfos, uint8_t *ws, uint32_t lds_bytes,
-                                                        uint32_t flags)
+                                                        rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,
+                                                        uint32_t lds_bytes, uint32_t flags)
 {
     __shared__ gen::BatchLds S;
     const uint32_t i = blockIdx.x;
     const rr_desc d = desc[i];
-    if (!desc_usable(d, maxw, maxh)) return;
+    if (!desc_usable(d, maxw, maxh, ws_bytes)) return;
     generic_entry(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), S, lds_bytes, flags);
 }
 
@@ -357,7 +369,6 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
                                                 size_t workspace_bytes, void *stream, void *graph_done_event,
                                                 void *loop_done_event)
 {
-    (void)workspace_bytes;
     if (n == 0) return RR_OK;
     if (!desc || !move_arena || !group_arena || !sinfos || !batch_arena || !step_arena || !binfos || !workspace)
         return RR_E_INVAL;
@@ -368,11 +379,13 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     hipStream_t st = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
     hipLaunchKernelGGL(k_graph_many, dim3(n), dim3(fast::kGT), P.graph_lds, st, desc, (int)max_w, (int)max_h,
-                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, P.graph_lds, flags);
+                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes,
+                       P.graph_lds, flags);
     if (graph_done_event && hipEventRecord((hipEvent_t)graph_done_event, st) != hipSuccess) return RR_E_DEVICE;
 #define RR_LOOP_MANY(SS, FF)                                                                                       \
     hipLaunchKernelGGL((k_loop_many<SS, FF>), dim3(n), dim3(kWave), P.loop_lds, st, desc, (int)max_w, (int)max_h,  \
-                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, P.loop_lds)
+                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws,                       \
+                       (uint64_t)workspace_bytes, P.loop_lds)
 #define RR_LOOP_MANY_F(SS)                                                                                         \
     switch (flags & 0xFFu) {                                                                                       \
     case RR_LAMBDA_LINE_OR_COL: RR_LOOP_MANY(SS, RR_LAMBDA_LINE_OR_COL); break;                                    \
@@ -388,7 +401,8 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
 #undef RR_LOOP_MANY
     if (loop_done_event && hipEventRecord((hipEvent_t)loop_done_event, st) != hipSuccess) return RR_E_DEVICE;
     hipLaunchKernelGGL(k_generic_many, dim3(n), dim3(kWave), P.gen_lds, st, desc, (int)max_w, (int)max_h, move_arena,
-                       group_arena, sinfos, batch_arena, step_arena, binfos, ws, P.gen_lds, flags);
+                       group_arena, sinfos, batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes, P.gen_lds,
+                       flags);
     return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
 }
 

@@ -356,6 +356,26 @@ class ClassedBuffers:
                 grown = True
         return grown
 
+    OUTPUTS = ("sinfo", "binfo", "moves", "groups", "final", "steps", "batches", "desc")
+
+    def outputs(self):
+        """Device copies of every array a run writes, per class: solve and batching infos, moves,
+        group offsets, final grids, steps, batch offsets and the planned descriptors."""
+        return [{k: getattr(mb, k).clone() for k in self.OUTPUTS} for _, _, mb in self.parts]
+
+    def poison_outputs(self, byte=0x5A):
+        """Fill every output array except the descriptors with ``byte`` (a device fill), so that
+        a later run that leaves something unwritten is seen when its outputs are compared."""
+        for _, _, mb in self.parts:
+            for k in self.OUTPUTS[:-1]:
+                getattr(mb, k).view(torch.uint8).fill_(byte)
+        return self
+
+    @staticmethod
+    def same_outputs(a, b) -> bool:
+        """Byte equality of two ``outputs()`` snapshots (compared on the device)."""
+        return len(a) == len(b) and all(torch.equal(x[k], y[k]) for x, y in zip(a, b) for k in x)
+
     def infos(self):
         """(solve_infos, batch_infos) in the caller's shot order."""
         s = np.zeros((self.n, SOLVE_INFO_WORDS), np.uint32)
