@@ -211,6 +211,31 @@ rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc, uint32_t m
 rr_status rr_plan_many(uint32_t n, rr_desc *desc, const rr_solve_info *infos, uint64_t step_pool,
                        uint64_t batch_pool, uint64_t ws_pool_bytes, uint64_t *totals, void *stream);
 
+/* ------------------------------------------------------------------------------------------ */
+/* Batching with no allocation                                                                 */
+
+/* Size of the library's own batching workspace: one file-scope device array per GPU, held from
+ * the library's load until the process ends. */
+#define RR_NOALLOC_WORKSPACE_BYTES (64u << 20)
+
+/* rr_batch_moves for callers that cannot allocate device memory (code under stream or graph
+ * capture, serving loops that must not call the allocator, harnesses that forbid it): same
+ * arguments, semantics and results, but the workspace is the library's array on the current
+ * device instead of a caller buffer.  The call itself allocates and frees nothing.
+ *   - Returns RR_E_NOMEM, before touching the device, when
+ *     rr_batch_workspace_bytes(shape, move_cap, step_cap) exceeds RR_NOALLOC_WORKSPACE_BYTES
+ *     (every grid up to 256 x 256 with move_cap = 2*(x1-x0)*(y1-y0) fits for step_cap up to
+ *     3 million); RR_E_DEVICE when the array's device address cannot be obtained.
+ *   - The first call on a device looks up the array's address on that device (once per
+ *     device, with that device current); later calls make no device query.
+ *   - Every call on one device shares that device's array, which keeps the last call's
+ *     contents (the kernels initialise whatever they read).  Calls that overlap on one device
+ *     race: serialise them (one stream, or events between streams). */
+rr_status rr_batch_moves_noalloc(rr_shape shape, const rr_move *moves, const uint32_t *group_off,
+                                 const rr_solve_info *sinfo, uint32_t move_cap, uint32_t flags,
+                                 uint32_t *batch_off, uint32_t batch_cap,
+                                 uint32_t *steps, uint32_t step_cap, rr_batch_info *binfo, void *stream);
+
 /* Library version string (host). */
 const char *rr_version(void);
 

@@ -18,6 +18,7 @@ RR_E_INVAL, RR_E_CAPACITY, RR_E_DEVICE, RR_E_NOMEM, RR_E_INTERNAL, RR_E_UNSUPPOR
 RR_LAMBDA_LINE_OR_COL, RR_LAMBDA_ALONG, RR_LAMBDA_NONE = 0, 1, 2
 RR_BATCH_GENERIC = 1 << 16
 RR_MAX_SIDE = 256
+RR_NOALLOC_WORKSPACE_BYTES = 64 << 20
 STATUS_NAMES = {0: "RR_OK", 1: "RR_INFEASIBLE", -1: "RR_E_INVAL", -2: "RR_E_CAPACITY", -3: "RR_E_DEVICE",
                 -4: "RR_E_NOMEM", -5: "RR_E_INTERNAL", -6: "RR_E_UNSUPPORTED"}
 
@@ -62,6 +63,7 @@ _SIGS = {
     "rr_solve": ([rr_shape, _P, _P, _U32, _P, _U32, _P, _P, _P, _SZ, _P], C.c_int),
     "rr_batch_workspace_bytes": ([rr_shape, _U32, _U32], _SZ),
     "rr_batch_moves": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P, _SZ, _P], C.c_int),
+    "rr_batch_moves_noalloc": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P], C.c_int),
     "rr_solve_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _P, _P, _P], C.c_int),
     "rr_batch_moves_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "rr_plan_many": ([_U32, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
@@ -141,6 +143,14 @@ def rr_batch_moves(shape, moves, group_off, sinfo, move_cap, flags, batch_off, b
                               int(flags), _ptr(batch_off), int(batch_cap), _ptr(steps), int(step_cap),
                               _ptr(binfo), _ptr(workspace), int(workspace_bytes), _stream(stream))
     return _check(rc, "rr_batch_moves") if check else rc
+
+
+def rr_batch_moves_noalloc(shape, moves, group_off, sinfo, move_cap, flags, batch_off, batch_cap, steps, step_cap,
+                           binfo, stream=None, check=True) -> int:
+    rc = lib().rr_batch_moves_noalloc(_shape(shape), _ptr(moves), _ptr(group_off), _ptr(sinfo), int(move_cap),
+                                      int(flags), _ptr(batch_off), int(batch_cap), _ptr(steps), int(step_cap),
+                                      _ptr(binfo), _stream(stream))
+    return _check(rc, "rr_batch_moves_noalloc") if check else rc
 
 
 def rr_solve_many(n, desc, max_w, max_h, occ_arena, move_arena, group_arena, final_arena, infos,

@@ -19,6 +19,7 @@
 #include "rr_batch_loop.hpp"
 
 #include <atomic>
+#include <mutex>
 
 static_assert(sizeof(rr_desc) == 80, "rr_desc layout");
 static_assert(sizeof(rr_move) == 8, "rr_move layout");
@@ -414,4 +415,47 @@ extern "C" rr_status rr_batch_moves_many(uint32_t n, const rr_desc *desc, uint32
 {
     return rr_batch_moves_many_staged(n, desc, max_w, max_h, move_arena, group_arena, sinfos, flags, batch_arena,
                                       step_arena, binfos, workspace, workspace_bytes, stream, nullptr, nullptr);
+}
+
+// ---- batching with no allocation: the workspace is a file-scope device array
+
+// One per device (the code object is loaded on every device the library runs on).  In host code
+// `scratch` names a host-side stand-in, never the device memory: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) uint8_t scratch[RR_NOALLOC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::once_flag scratch_once[kMaxScratchDevices];
+void *scratch_addr[kMaxScratchDevices];
+hipError_t scratch_err[kMaxScratchDevices];
+
+// device address of the current device's scratch array (nullptr on failure)
+void *scratch_for_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    std::call_once(scratch_once[dev], [dev] {
+        void *p = nullptr;
+        scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        scratch_addr[dev] = scratch_err[dev] == hipSuccess ? p : nullptr;
+    });
+    return scratch_addr[dev];
+}
+}  // namespace
+
+extern "C" rr_status rr_batch_moves_noalloc(rr_shape shape, const rr_move *moves, const uint32_t *group_off,
+                                            const rr_solve_info *sinfo, uint32_t move_cap, uint32_t flags,
+                                            uint32_t *batch_off, uint32_t batch_cap, uint32_t *steps,
+                                            uint32_t step_cap, rr_batch_info *binfo, void *stream)
+{
+    if (!(shape.w >= 1 && shape.h >= 1 && shape.x0 < shape.x1 && shape.x1 <= shape.w && shape.y0 < shape.y1 &&
+          shape.y1 <= shape.h))
+        return RR_E_INVAL;
+    if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
+    if (rr_batch_workspace_bytes(shape, move_cap, step_cap) > (size_t)RR_NOALLOC_WORKSPACE_BYTES) return RR_E_NOMEM;
+    void *ws = scratch_for_current_device();
+    if (!ws) return RR_E_DEVICE;
+    return rr_batch_moves(shape, moves, group_off, sinfo, move_cap, flags, batch_off, batch_cap, steps, step_cap,
+                          binfo, ws, (size_t)RR_NOALLOC_WORKSPACE_BYTES, stream);
 }

@@ -69,3 +69,14 @@ def test_null_outputs_and_small_workspace_rejected():
     assert rc == rr.RR_E_NOMEM
     rc = rr.rr_batch_moves(shape, 8, 8, 8, 100, 7, 8, 100, 8, 100, 8, 8, need, stream=0, check=False)
     assert rc == rr.RR_E_INVAL
+
+
+def test_noalloc_refuses_oversized_workspace_before_launch():
+    shape = (256, 256, 38, 38, 217, 217)
+    mc = 2 * 179 * 179
+    fits = rr.rr_batch_workspace_bytes(shape, mc, 3_000_000)
+    assert fits <= rr.RR_NOALLOC_WORKSPACE_BYTES < rr.rr_batch_workspace_bytes(shape, mc, 3_100_000)
+    rc = rr.rr_batch_moves_noalloc(shape, 8, 8, 8, mc, 0, 8, 3_100_000, 8, 3_100_000, 8, stream=0, check=False)
+    assert rc == rr.RR_E_NOMEM
+    rc = rr.rr_batch_moves_noalloc((300, 300, 1, 1, 2, 2), 8, 8, 8, 2, 0, 8, 8, 8, 8, 8, stream=0, check=False)
+    assert rc == rr.RR_E_UNSUPPORTED
