@@ -62,7 +62,8 @@ def lib():
         L.rr_oracle_solve.argtypes = [C.POINTER(Shape), P, P, C.c_uint32, P, C.c_uint32, P, C.POINTER(SolveInfo)]
         L.rr_oracle_solve.restype = C.c_int
         L.rr_oracle_solve_trace.argtypes = [C.POINTER(Shape), P, P, C.c_uint32, P, C.c_uint32, P,
-                                            C.POINTER(SolveInfo), P, C.c_uint32, C.POINTER(C.c_uint32)]
+                                            C.POINTER(SolveInfo), C.c_uint32, P, C.c_uint32,
+                                            C.POINTER(C.c_uint32)]
         L.rr_oracle_solve_trace.restype = C.c_int
         L.rr_oracle_batch_moves.argtypes = [C.POINTER(Shape), P, P, C.POINTER(SolveInfo), C.c_uint32,
                                             P, C.c_uint32, P, C.c_uint32, C.POINTER(BatchInfo)]
@@ -101,11 +102,16 @@ def e1d_moves(p, b: int, t: int):
     return list(zip(src[:n].tolist(), dst[:n].tolist()))
 
 
-def solve(shape, occ, move_cap=None, group_cap=None, trace=False):
+REDREC_PARALLEL, REDREC_SERIAL = 0, 1
+
+
+def solve(shape, occ, move_cap=None, group_cap=None, trace=False, serial=False):
     """Run the oracle solve on packed rows ``occ`` (uint64[h][ws]).
 
-    Returns a dict: rc, status, moves (uint16[n][4] = sx,sy,dx,dy), group_off (uint32[g+1]),
-    final (uint64[h][ws]), n_steps, need_moves, need_groups and, with ``trace``, events."""
+    ``serial`` selects the serial order of Alg. 1 (donors solved after they donate) instead of
+    the parallel one of §III.D.  Returns a dict: rc, status, moves (uint16[n][4] = sx,sy,dx,dy),
+    group_off (uint32[g+1]), final (uint64[h][ws]), n_steps, need_moves, need_groups and, with
+    ``trace``, events."""
     sh = make_shape(shape)
     occ = np.ascontiguousarray(occ, dtype=np.uint64)
     w, h, x0, y0, x1, y1 = (int(v) for v in shape)
@@ -118,12 +124,15 @@ def solve(shape, occ, move_cap=None, group_cap=None, trace=False):
     final = np.zeros_like(occ)
     info = SolveInfo()
     out = {}
-    if trace:
+    if trace or serial:
         ev = (Event * (w + 1))()
         nev = C.c_uint32(0)
         rc = lib().rr_oracle_solve_trace(C.byref(sh), _ptr(occ), _ptr(moves), move_cap, _ptr(goff), group_cap,
-                                         _ptr(final), C.byref(info), C.cast(ev, C.c_void_p), w + 1, C.byref(nev))
-        out["events"] = [(e.donor, e.receiver, e.kase, e.k_bottom, e.count) for e in ev[:min(nev.value, w + 1)]]
+                                         _ptr(final), C.byref(info), REDREC_SERIAL if serial else REDREC_PARALLEL,
+                                         C.cast(ev, C.c_void_p), w + 1, C.byref(nev))
+        if trace:
+            out["events"] = [(e.donor, e.receiver, e.kase, e.k_bottom, e.count)
+                             for e in ev[:min(nev.value, w + 1)]]
     else:
         rc = lib().rr_oracle_solve(C.byref(sh), _ptr(occ), _ptr(moves), move_cap, _ptr(goff), group_cap,
                                    _ptr(final), C.byref(info))

@@ -30,6 +30,9 @@
 
 enum { O_OK = 0, O_INFEASIBLE = 1, O_E_INVAL = -1, O_E_CAPACITY = -2, O_E_NOMEM = -4, O_E_INTERNAL = -5 };
 enum { O_LAMBDA_LINE_OR_COL = 0, O_LAMBDA_ALONG = 1, O_LAMBDA_NONE = 2 };
+/* Order of Alg. 1: the parallel form of §III.D (every non-negative column solved from the
+ * outset; canonical) or the serial form of §III.C (donors solved after they donate). */
+enum { O_REDREC_PARALLEL = 0, O_REDREC_SERIAL = 1 };
 
 typedef struct { uint16_t w, h, x0, y0, x1, y1; } o_shape;
 typedef struct { uint16_t sx, sy, dx, dy; } o_move;
@@ -200,6 +203,9 @@ typedef struct {
     int *bp, *nb, *bh;         /* lower reservoir pool of column x, nearest-first; size; head */
     int *up, *nu, *uh;         /* upper reservoir pool of column x, nearest-first; size; head */
     o_src *mk; int *nm;        /* tokens marked for receiver x (row, donor); count */
+    int serial;                /* serial order of Alg. 1 (donors solved after they donate) */
+    int *solved;               /* central column already solved (serial order) */
+    int *dr;                   /* scratch rows of a donor solve */
     mlist L;
     o_event *ev; uint32_t ev_cap, n_ev;
     int status;
@@ -263,6 +269,37 @@ static long split_cost(const rr_state *S, int i, int j, int k, int d, int *rows)
     long cost = 0;
     for (int m = 0; m < c; ++m) cost += iabs(rows[m] - (S->y0 + m));
     return cost;
+}
+
+/* Solve donor column x in the serial order of Alg. 1 (its case 2 and case 3, and the columns
+ * still unsolved when the loop ends): exact 1D onto [y0, y1) over the tokens the column still
+ * holds -- its band tokens and what is left of its reservoir pool (the rest was handed to
+ * earlier receivers).  The unmatched tokens lie outside the band (exact-1D lemma) and become
+ * the column's pool again, nearest to the band first. */
+static void solve_donor(rr_state *S, int x)
+{
+    const int H = S->H, y0 = S->y0, y1 = S->y1, sh = S->sh;
+    int *r = S->dr, a = 0;
+    for (int m = S->nb[x] - 1; m >= S->bh[x]; --m) r[a++] = S->bp[x * H + m];   /* below, ascending */
+    for (int k = 0; k < S->na[x]; ++k) {
+        int y = S->q[x * H + k];
+        if (y >= y0 && y < y1) r[a++] = y;
+    }
+    for (int m = S->uh[x]; m < S->nu[x]; ++m) r[a++] = S->up[x * H + m];          /* above, ascending */
+    if (a < sh) { S->status = O_E_INTERNAL; return; }
+    int w = e1d_window(r, a, y0, sh);
+    int *src = (int *)malloc(sizeof(int) * (size_t)sh), *tgt = (int *)malloc(sizeof(int) * (size_t)sh);
+    if (!src || !tgt) { free(src); free(tgt); S->L.oom = 1; return; }
+    for (int k = 0; k < sh; ++k) { src[k] = r[w + k]; tgt[k] = y0 + k; }
+    size_t start = S->L.n;
+    emit_line(&S->L, 0, x, src, tgt, sh);
+    apply_moves(S->cell, S->W, &S->L, start);
+    ml_close_group(&S->L, start);
+    free(src); free(tgt);
+    S->nb[x] = S->bh[x] = S->nu[x] = S->uh[x] = 0;
+    for (int k = w - 1; k >= 0; --k) S->bp[x * H + S->nb[x]++] = r[k];
+    for (int k = w + sh; k < a; ++k) S->up[x * H + S->nu[x]++] = r[k];
+    S->solved[x] = 1;
 }
 
 /* Is pair (i, j) better than (bi, bj) under the pairing rule (§III.C): more tokens exchanged
@@ -346,13 +383,21 @@ static void redrec(rr_state *S)
     /* Columns with non-negative surplus are solved from the outset, in ascending x (§III.D).
      * A central one is solved by exact 1D onto [y0, y1); its unmatched tokens stay where they
      * are and form its donor pool: B below the band, nearest first, and U above it, nearest
-     * first.  A side column has nothing to solve; its reservoir tokens form its pool. */
+     * first.  A side column has nothing to solve; its reservoir tokens form its pool.
+     * Serial order (Alg. 1 as written): only the columns of zero surplus are solved here; a
+     * central donor keeps all its tokens until it is solved, and its pool is its reservoir
+     * tokens, nearest to the band first. */
     for (int x = 0; x < W; ++x) {
         S->nb[x] = S->nu[x] = S->bh[x] = S->uh[x] = S->nm[x] = 0;
+        S->solved[x] = 0;
         if (S->sigma[x] < 0) continue;
         const int *qx = S->q + x * H;
         int a = S->na[x];
-        if (x >= x0 && x < x1) {
+        if (x >= x0 && x < x1 && S->serial && S->sigma[x] > 0) {
+            for (int k = a - 1; k >= 0; --k) if (qx[k] < y0) S->bp[x * H + S->nb[x]++] = qx[k];
+            for (int k = 0; k < a; ++k) if (qx[k] >= y1) S->up[x * H + S->nu[x]++] = qx[k];
+        } else if (x >= x0 && x < x1) {
+            S->solved[x] = 1;
             int w = e1d_window(qx, a, y0, sh);
             for (int k = 0; k < sh; ++k) { src[k] = qx[w + k]; tgt[k] = y0 + k; }
             size_t start = S->L.n;
@@ -391,10 +436,16 @@ static void redrec(rr_state *S)
         int i = bi, j = bj;
         int avail = S->nb[i] - S->bh[i] + S->nu[i] - S->uh[i];
         int d = -S->sp[j];
-        if (avail != S->sp[i]) { S->status = O_E_INTERNAL; goto out; }
+        int unsolved = (i >= x0 && i < x1 && !S->solved[i]);   /* serial order only */
+        if (unsolved ? avail < S->sp[i] : avail != S->sp[i]) { S->status = O_E_INTERNAL; goto out; }
 
         if (S->sp[i] < d) {
-            /* Case 3: the donor's whole pool is marked for the receiver; nothing moves yet. */
+            /* Case 3: the donor's whole pool is marked for the receiver; nothing moves yet.  In
+             * the serial order the donor is solved first, and its pool is then its excess. */
+            if (unsolved) {
+                solve_donor(S, i);
+                if (S->status != O_OK || S->L.oom) goto out;
+            }
             int cnt = 0;
             for (int m = S->bh[i]; m < S->nb[i]; ++m) {
                 o_src t; t.y = S->bp[i * H + m]; t.origin = i; t.key = 0;
@@ -441,19 +492,34 @@ static void redrec(rr_state *S)
             S->n_ev++;
             solve_receiver(S, j, chosen, nc);
             if (S->status != O_OK) goto out;
+            /* Case 2 in the serial order: the donor, left with exactly sh tokens, is solved
+             * right after the receiver. */
+            if (kase == 2 && unsolved) {
+                solve_donor(S, i);
+                if (S->status != O_OK || S->L.oom) goto out;
+            }
         }
     }
+    /* Serial order: the columns still unsolved when every receiver is saturated are solved
+     * last, in ascending x; their excess stays in the reservoir. */
+    if (S->serial)
+        for (int x = x0; x < x1; ++x)
+            if (!S->solved[x] && S->sigma[x] > 0) {
+                solve_donor(S, x);
+                if (S->status != O_OK || S->L.oom) goto out;
+            }
 out:
     free(p); free(src); free(tgt); free(rows); free(chosen);
 }
 
 static int solve_impl(const o_shape *shape, const uint64_t *occ, o_move *moves, uint32_t move_cap,
                       uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ, o_solve_info *info,
-                      o_event *ev, uint32_t ev_cap, uint32_t *n_ev)
+                      uint32_t flags, o_event *ev, uint32_t ev_cap, uint32_t *n_ev)
 {
-    if (!shape_ok(shape) || !occ || !info) return O_E_INVAL;
+    if (!shape_ok(shape) || !occ || !info || flags > O_REDREC_SERIAL) return O_E_INVAL;
     rr_state S;
     memset(&S, 0, sizeof S);
+    S.serial = (flags == O_REDREC_SERIAL);
     S.W = shape->w; S.H = shape->h;
     S.x0 = shape->x0; S.y0 = shape->y0; S.x1 = shape->x1; S.y1 = shape->y1;
     S.sw = S.x1 - S.x0; S.sh = S.y1 - S.y0;
@@ -473,10 +539,12 @@ static int solve_impl(const o_shape *shape, const uint64_t *occ, o_move *moves, 
     S.nu = (int *)calloc((size_t)W, sizeof(int));
     S.uh = (int *)calloc((size_t)W, sizeof(int));
     S.nm = (int *)calloc((size_t)W, sizeof(int));
+    S.solved = (int *)calloc((size_t)W, sizeof(int));
+    S.dr = (int *)malloc(sizeof(int) * (size_t)(H + 1));
     ml_init(&S.L);
     int rc = O_OK;
     if (!S.cell || !S.q || !S.bp || !S.up || !S.mk || !S.na || !S.sigma || !S.sp || !S.nb || !S.bh ||
-        !S.nu || !S.uh || !S.nm || S.L.oom) { rc = O_E_NOMEM; goto done; }
+        !S.nu || !S.uh || !S.nm || !S.solved || !S.dr || S.L.oom) { rc = O_E_NOMEM; goto done; }
 
     for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x)
@@ -519,6 +587,7 @@ write_final:
 done:
     free(S.cell); free(S.q); free(S.bp); free(S.up); free(S.mk);
     free(S.na); free(S.sigma); free(S.sp); free(S.nb); free(S.bh); free(S.nu); free(S.uh); free(S.nm);
+    free(S.solved); free(S.dr);
     ml_free(&S.L);
     return rc;
 }
@@ -527,15 +596,17 @@ done:
 int rr_oracle_solve(const o_shape *shape, const uint64_t *occ, o_move *moves, uint32_t move_cap,
                     uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ, o_solve_info *info)
 {
-    return solve_impl(shape, occ, moves, move_cap, group_off, group_cap, final_occ, info, NULL, 0, NULL);
+    return solve_impl(shape, occ, moves, move_cap, group_off, group_cap, final_occ, info, O_REDREC_PARALLEL,
+                      NULL, 0, NULL);
 }
 
-/* Same solve, also reporting the donor/receiver loop's events in order. */
+/* Same solve, also reporting the donor/receiver loop's events in order; flags selects the
+ * order of Alg. 1 (O_REDREC_PARALLEL or O_REDREC_SERIAL). */
 int rr_oracle_solve_trace(const o_shape *shape, const uint64_t *occ, o_move *moves, uint32_t move_cap,
                           uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ, o_solve_info *info,
-                          o_event *events, uint32_t event_cap, uint32_t *n_events)
+                          uint32_t flags, o_event *events, uint32_t event_cap, uint32_t *n_events)
 {
-    return solve_impl(shape, occ, moves, move_cap, group_off, group_cap, final_occ, info,
+    return solve_impl(shape, occ, moves, move_cap, group_off, group_cap, final_occ, info, flags,
                       events, event_cap, n_events);
 }
 

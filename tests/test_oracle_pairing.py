@@ -84,20 +84,30 @@ def line_cost(rows, y0):
     return sum(abs(r - (y0 + m)) for m, r in enumerate(sorted(rows)))
 
 
-def naive_pair_loop(shape, dense, split_check=False, subset_limit=12):
+def naive_pair_loop(shape, dense, split_check=False, subset_limit=12, serial=False):
     """Events (donor, receiver, case, count) of the loop, or None when the surpluses sum below
-    zero (the instance is refused before any move)."""
+    zero (the instance is refused before any move).
+
+    ``serial``: Alg. 1 in its serial order -- a central donor is not solved at the outset; its
+    pool is its reservoir tokens (nearest the band first), it hands tokens over from that pool,
+    and it is solved when it settles (case 2 after the receiver, case 3 before its tokens are
+    marked: an exact-1D window over the tokens it still holds, whose unmatched ones are then
+    marked)."""
     w, h, x0, y0, x1, y1 = shape
     sh = y1 - y0
     cols = counts_after_row_pass(shape, dense)
     sig = [len(c) - (sh if x0 <= x < x1 else 0) for x, c in enumerate(cols)]
     if sum(sig) < 0:
         return None, []
-    below, above, own, marked = {}, {}, {}, {}
+    below, above, own, marked, band = {}, {}, {}, {}, {}
     for x in range(w):
         if sig[x] >= 0:
             r = cols[x]
-            if x0 <= x < x1:
+            if serial and x0 <= x < x1 and sig[x] > 0:
+                below[x] = [y for y in reversed(r) if y < y0]
+                above[x] = [y for y in r if y >= y1]
+                band[x] = [y for y in r if y0 <= y < y1]
+            elif x0 <= x < x1:
                 s = best_window(r, y0, sh)
                 below[x] = list(reversed(r[:s]))          # nearest the band first
                 above[x] = r[s + sh:]
@@ -142,6 +152,10 @@ def naive_pair_loop(shape, dense, split_check=False, subset_limit=12):
             sp[j] = 0
             events.append((i, j, kase, k_sel, cnt))
         else:
+            if i in band:                                 # serial order: solve the donor first
+                r = sorted(below[i] + band.pop(i) + above[i])
+                s = best_window(r, y0, sh)
+                below[i], above[i] = list(reversed(r[:s])), r[s + sh:]
             marked[j] += below[i] + above[i]
             below[i], above[i] = [], []
             sp[j] += si
