@@ -79,6 +79,17 @@ typedef struct {
  * registers while it runs (that instance is then redone from its inputs). */
 #define RR_BATCH_GENERIC      (1u << 16)
 
+/* Order of Alg. 1 in rr_solve (flags bits 0..7): the parallel form of §III.D, where every
+ * column of zero or positive surplus is solved from the outset and a donor hands over its
+ * excess (the default), or the serial form of §III.C, where only zero-surplus columns are
+ * solved first, a donor hands over its reservoir tokens nearest the target first and is solved
+ * when it settles (after its receiver when both settle, before its tokens are marked when it
+ * is exhausted), and donors still unsolved after the loop are solved last, in ascending x.
+ * Both orders pair the same columns in the same order; they differ in which donor tokens move
+ * and in the order of the groups. */
+#define RR_REDREC_PARALLEL 0u
+#define RR_REDREC_SERIAL   1u
+
 /* Largest grid side the device kernels take. */
 #define RR_MAX_SIDE 256u
 
@@ -97,6 +108,7 @@ size_t rr_solve_workspace_bytes(rr_shape shape);
  *                    surplus with moves, one per receiver column in the order it was saturated.
  *   final_occ  [out] bit rows of the grid after all moves (H*ws words).
  *   info       [out] one rr_solve_info.
+ *   flags      [in]  RR_REDREC_PARALLEL or RR_REDREC_SERIAL (any other value: RR_E_INVAL).
  * An instance is solved iff F = N - D - (x1-x0)*(y1-y0) >= 0, decided before any move: N is
  * the number of tokens and D the number of target-row tokens beyond the target width,
  * counted only when the target leaves side columns (the row pre-pass parks those tokens in
@@ -108,7 +120,7 @@ size_t rr_solve_workspace_bytes(rr_shape shape);
 rr_status rr_solve(rr_shape shape, const uint64_t *occ,
                    rr_move *moves, uint32_t move_cap,
                    uint32_t *group_off, uint32_t group_cap,
-                   uint64_t *final_occ, rr_solve_info *info,
+                   uint64_t *final_occ, rr_solve_info *info, uint32_t flags,
                    void *workspace, size_t workspace_bytes, void *stream);
 
 /* Bytes of device workspace rr_batch_moves needs for this shape and these capacities. */
@@ -169,11 +181,14 @@ typedef struct {
 
 /* Solve n instances in one launch; instance i reads occ_arena + desc[i].occ_off and writes
  * moves/group offsets/final bit rows at its offsets and infos[i].  Results are bit-identical to
- * n calls of rr_solve.  max_w / max_h bound every instance's grid (they pick the kernel
- * variant; an instance beyond them gets RR_E_INVAL). */
+ * n calls of rr_solve with the same flags (the order of Alg. 1, as in rr_solve).  max_w / max_h
+ * bound every instance's grid (they pick the kernel variant; an instance beyond them gets
+ * RR_E_INVAL).  workspace / workspace_bytes: n * rr_solve_workspace_bytes of the largest grid
+ * (0 for grids up to RR_MAX_SIDE: NULL is then accepted). */
 rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
                         const uint64_t *occ_arena, rr_move *move_arena, uint32_t *group_arena,
-                        uint64_t *final_arena, rr_solve_info *infos, void *stream);
+                        uint64_t *final_arena, rr_solve_info *infos, uint32_t flags,
+                        void *workspace, size_t workspace_bytes, void *stream);
 
 /* Batch the moves of n solved instances in one launch (same semantics and flags as
  * rr_batch_moves; the LDS budget in flags bits 8..15 applies to every instance).

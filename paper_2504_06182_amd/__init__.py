@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 RR_OK, RR_INFEASIBLE = 0, 1
 RR_E_INVAL, RR_E_CAPACITY, RR_E_DEVICE, RR_E_NOMEM, RR_E_INTERNAL, RR_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 RR_LAMBDA_LINE_OR_COL, RR_LAMBDA_ALONG, RR_LAMBDA_NONE = 0, 1, 2
+RR_REDREC_PARALLEL, RR_REDREC_SERIAL = 0, 1
 RR_BATCH_GENERIC = 1 << 16
 RR_MAX_SIDE = 256
 RR_NOALLOC_WORKSPACE_BYTES = 64 << 20
@@ -60,11 +61,11 @@ _SZ = C.c_size_t
 _SIGS = {
     "rr_version": ([], C.c_char_p),
     "rr_solve_workspace_bytes": ([rr_shape], _SZ),
-    "rr_solve": ([rr_shape, _P, _P, _U32, _P, _U32, _P, _P, _P, _SZ, _P], C.c_int),
+    "rr_solve": ([rr_shape, _P, _P, _U32, _P, _U32, _P, _P, _U32, _P, _SZ, _P], C.c_int),
     "rr_batch_workspace_bytes": ([rr_shape, _U32, _U32], _SZ),
     "rr_batch_moves": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P, _SZ, _P], C.c_int),
     "rr_batch_moves_noalloc": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P], C.c_int),
-    "rr_solve_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _P, _P, _P], C.c_int),
+    "rr_solve_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _P, _P, _U32, _P, _SZ, _P], C.c_int),
     "rr_batch_moves_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "rr_plan_many": ([_U32, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
     "rr_batch_moves_many_staged": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P, _P, _P],
@@ -130,10 +131,11 @@ def rr_batch_workspace_bytes(shape, move_cap: int, step_cap: int) -> int:
     return int(lib().rr_batch_workspace_bytes(_shape(shape), int(move_cap), int(step_cap)))
 
 
-def rr_solve(shape, occ, moves, move_cap, group_off, group_cap, final_occ, info,
+def rr_solve(shape, occ, moves, move_cap, group_off, group_cap, final_occ, info, flags=RR_REDREC_PARALLEL,
              workspace=None, workspace_bytes=0, stream=None, check=True) -> int:
     rc = lib().rr_solve(_shape(shape), _ptr(occ), _ptr(moves), int(move_cap), _ptr(group_off), int(group_cap),
-                        _ptr(final_occ), _ptr(info), _ptr(workspace), int(workspace_bytes), _stream(stream))
+                        _ptr(final_occ), _ptr(info), int(flags), _ptr(workspace), int(workspace_bytes),
+                        _stream(stream))
     return _check(rc, "rr_solve") if check else rc
 
 
@@ -154,9 +156,10 @@ def rr_batch_moves_noalloc(shape, moves, group_off, sinfo, move_cap, flags, batc
 
 
 def rr_solve_many(n, desc, max_w, max_h, occ_arena, move_arena, group_arena, final_arena, infos,
-                  stream=None, check=True) -> int:
+                  flags=RR_REDREC_PARALLEL, workspace=None, workspace_bytes=0, stream=None, check=True) -> int:
     rc = lib().rr_solve_many(int(n), _ptr(desc), int(max_w), int(max_h), _ptr(occ_arena), _ptr(move_arena),
-                             _ptr(group_arena), _ptr(final_arena), _ptr(infos), _stream(stream))
+                             _ptr(group_arena), _ptr(final_arena), _ptr(infos), int(flags), _ptr(workspace),
+                             int(workspace_bytes), _stream(stream))
     return _check(rc, "rr_solve_many") if check else rc
 
 

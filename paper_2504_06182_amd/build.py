@@ -20,18 +20,44 @@ def hipcc() -> str:
     return p
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source for gfx950 into paper_2504_06182_amd/librr.so (always rebuilds)."""
+OBJ_DIR = os.path.join(ROOT, "_build")
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every HIP source for gfx950 into paper_2504_06182_amd/librr.so.
+
+    Each source is compiled to an object in its own hipcc process (in parallel), then linked.
+    By default every source is recompiled; ``incremental`` reuses an object in ``_build/`` that
+    is newer than its source and every header."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    flags = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"),
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    objs = [os.path.join(OBJ_DIR, os.path.basename(src) + ".o") for src in SOURCES]
+    newest_header = max(os.path.getmtime(h) for h in HEADERS)
+    procs = []
+    for src, obj in zip(SOURCES, objs):
+        if (incremental and os.path.exists(obj)
+                and os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header)):
+            continue
+        tmp = obj + ".tmp%d" % os.getpid()
+        procs.append((subprocess.Popen([hipcc(), *flags, "-c", src, "-o", tmp], stdout=subprocess.PIPE,
+                                       stderr=subprocess.PIPE, text=True), tmp, obj))
+    errs = []
+    for p, tmp, obj in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            errs.append(out + err)
+            continue
+        os.replace(tmp, obj)
+        if verbose and err:
+            print(err)
+    if errs:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-I", os.path.join(ROOT, "include"),
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           *SOURCES, "-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    r = subprocess.run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp],
+                       capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    if verbose and r.stderr:
-        print(r.stderr)
+        raise RuntimeError("hipcc link failed:\n" + r.stdout + r.stderr)
     os.replace(tmp, LIB)
     return LIB
 
@@ -44,4 +70,5 @@ def stale() -> bool:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -24,7 +24,9 @@ namespace rr {
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / kWave;
 
-enum { M_STEPS = 0, M_NEV = 1, M_ERR = 2 };
+enum { M_STEPS = 0, M_NEV = 1, M_ERR = 2, M_CNT = 3 };
+
+constexpr uint32_t kOrderSerial = 1u;   // RR_REDREC_SERIAL
 
 template <int S>
 struct SolveLds {
@@ -35,7 +37,12 @@ struct SolveLds {
     int rowW[S], rowT0[S], rowN[S], rowR[S], rowCnt[S], rowOff[S];
     int colA[S], colW[S], colU[S], colCnt[S], colOff[S], sp[S], sig[S], bcnt[S], ubeg[S];
     int mNb[S], mSb[S], mNt[S], mSt[S];
+    int cNb[S], cNbd[S];     // eligible tokens below the band / inside it, per column
+    int8_t dsol[S];          // column solved (the serial order leaves central donors unsolved)
     int16_t evI[S + 1], evJ[S + 1], evK[S + 1], evC[S + 1], evBlo[S + 1], evBhi[S + 1], evUlo[S + 1], evUhi[S + 1];
+    // donor solved with the event (serial order): window start over its remaining tokens, and
+    // its remaining pool bounds at that moment ([0,bc) below, [ub,a) above); evDW < 0: none
+    int16_t evDW[S + 1], evDbc[S + 1], evDub[S + 1];
     int P[kWaves][S + 1];
     int Q[kWaves][S + 2];
     uint64_t rkey[S];
@@ -47,6 +54,7 @@ struct SolveLds {
 
 struct SolveArgs {
     int W, H, x0, y0, x1, y1;
+    uint32_t flags;
     const uint64_t *occ;
     rr_move *moves;
     uint32_t move_cap;
@@ -197,6 +205,19 @@ __device__ __forceinline__ void emit_line_wave(const SolveArgs &A, const int *P,
     }
 }
 
+// Rows a donor still holds in the serial order: its eligible list F[0..a) (sorted) minus what
+// it handed over -- F[0,bc) below the band, its band tokens F[nb0, nb0+nbd), F[ub,a) above --
+// written to R in order; returns their count.
+__device__ __forceinline__ int remaining_rows_wave(const int *F, int a, int bc, int nb0, int nbd, int ub, int *R)
+{
+    const int lane = lane_id();
+    const int n1 = bc, n2 = nbd, n3 = a - ub;
+    for (int m = lane; m < n1 + n2 + n3; m += kWave)
+        R[m] = m < n1 ? F[m] : (m < n1 + n2 ? F[nb0 + (m - n1)] : F[ub + (m - n1 - n2)]);
+    wave_sync();
+    return n1 + n2 + n3;
+}
+
 // ------------------------------------------------------------------------------------------
 // donor/receiver loop (Alg. 1 main loop, pairing rule of §III.C), run by wave 0
 
@@ -256,8 +277,21 @@ __device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
         int *Q0 = L.Q[0];
         compact_bits_wave(&L.elig[i * hs], hs, P0);
         prefix_sums_wave(P0, ai, Q0);
+        int dw = -1, dbc = 0, dub = 0;
+        if (si < d && !L.dsol[i]) {
+            // serial order, case 3: the donor is solved first over the tokens it still holds;
+            // its unmatched ones (outside the band, exact-1D lemma) form the pool then marked
+            int *R = L.P[1], *RQ = L.Q[1];
+            const int nb0 = L.cNb[i], nbd = L.cNbd[i];
+            const int ar = remaining_rows_wave(P0, ai, bc, nb0, nbd, ub, R);
+            const int w = e1d_window_wave(R, RQ, ar, y0, sh);
+            if (w > bc || w + sh < bc + nbd) err = 1;
+            dw = w; dbc = bc; dub = ub;
+        }
         if (si < d) {
             // case 3: the donor's whole pool is marked for the receiver
+            const int bc = dw >= 0 ? dw : L.bcnt[i];
+            const int ub = dw >= 0 ? dub + (dw + sh - dbc - L.cNbd[i]) : L.ubeg[i];
             if (lane == 0) {
                 L.mNb[j] += bc;
                 L.mSb[j] += Q0[bc];
@@ -267,6 +301,8 @@ __device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
                 L.evBlo[nev] = 0; L.evBhi[nev] = (int16_t)bc; L.evUlo[nev] = (int16_t)ub; L.evUhi[nev] = (int16_t)ai;
                 L.bcnt[i] = 0; L.ubeg[i] = ai;
                 L.sp[j] = si - d; L.sp[i] = 0;
+                L.evDW[nev] = (int16_t)dw; L.evDbc[nev] = (int16_t)dbc; L.evDub[nev] = (int16_t)dub;
+                L.dsol[i] = 1;
             }
         } else {
             // cases 1-2: d tokens, the k nearest below the band and the d-k nearest above it,
@@ -308,13 +344,19 @@ __device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
             }
             bk = wave_min_u64(bk);
             const int k = 0xFFFF - (int)(bk & 0xFFFFull);
+            // serial order, case 2: the donor, left with exactly sh tokens, is solved after the
+            // receiver (window 0 over what it holds; nothing of it stays in the reservoir)
+            const bool dsolve = si == d && !L.dsol[i];
             if (lane == 0) {
                 L.evI[nev] = (int16_t)i; L.evJ[nev] = (int16_t)j; L.evC[nev] = (int16_t)(si == d ? 2 : 1);
                 L.evK[nev] = (int16_t)k;
                 L.evBlo[nev] = (int16_t)(bc - k); L.evBhi[nev] = (int16_t)bc;
                 L.evUlo[nev] = (int16_t)ub; L.evUhi[nev] = (int16_t)(ub + d - k);
-                L.bcnt[i] = bc - k; L.ubeg[i] = ub + d - k;
+                L.bcnt[i] = dsolve ? 0 : bc - k; L.ubeg[i] = dsolve ? ai : ub + d - k;
                 L.sp[i] = si - d; L.sp[j] = 0;
+                L.evDW[nev] = (int16_t)(dsolve ? 0 : -1);
+                L.evDbc[nev] = (int16_t)(bc - k); L.evDub[nev] = (int16_t)(ub + d - k);
+                if (dsolve) L.dsol[i] = 1;
             }
         }
         ++nev;
@@ -333,6 +375,7 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     const int sw = x1 - x0, sh = y1 - y0;
     const int ws = (W + 63) >> 6, hs = (H + 63) >> 6;
     const bool side = (x0 > 0 || x1 < W);
+    const bool serial = (A.flags & 0xFFu) == kOrderSerial;
     int *P = L.P[wid];
     int *Q = L.Q[wid];
 
@@ -429,7 +472,7 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     if (tid < W) {
         const int x = tid;
         const bool central = (x >= x0 && x < x1);
-        int a = 0, nbelow = 0;
+        int a = 0, nbelow = 0, nband = 0;
         for (int sl = 0; sl < hs; ++sl) {
             const uint64_t c = L.cols[x * hs + sl];
             const uint64_t band = range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
@@ -437,17 +480,23 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
             L.elig[x * hs + sl] = e;
             a += popc(e);
             nbelow += popc(e & low_mask(y0 - 64 * sl));
+            nband += popc(e & band);
         }
         const int sigma = a - (central ? sh : 0);
         L.colA[x] = a; L.sig[x] = sigma; L.sp[x] = sigma; L.colCnt[x] = 0;
-        L.bcnt[x] = nbelow; L.ubeg[x] = nbelow;
+        // pool of a donor not yet solved: its reservoir tokens, below [0, nbelow) and above
+        // [nbelow + nband, a) (side columns: no band tokens)
+        L.bcnt[x] = nbelow; L.ubeg[x] = nbelow + nband;
+        L.cNb[x] = nbelow; L.cNbd[x] = nband;
+        L.dsol[x] = (int8_t)!(serial && central && sigma > 0);
         L.mNb[x] = 0; L.mSb[x] = 0; L.mNt[x] = 0; L.mSt[x] = 0;
     }
     __syncthreads();
 
-    // ---- columns of non-negative surplus, solved from the outset (§III.D) -----------------
+    // ---- columns of non-negative surplus, solved from the outset (§III.D); the serial order
+    //      of Alg. 1 solves only the columns of zero surplus here ------------------------------
     for (int x = x0 + wid; x < x1; x += kWaves) {
-        if (L.sig[x] < 0) continue;
+        if (L.sig[x] < 0 || !L.dsol[x]) continue;
         const int a = compact_bits_wave(&L.elig[x * hs], hs, P);
         const int w0 = e1d_window_wave(P, Q, a, y0, sh);
         int u = 0, c = 0, st = 0;
@@ -488,10 +537,11 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     __syncthreads();
     const int nev = L.misc[M_NEV];
 
-    // ---- receiver solves, in the order receivers were saturated ------------------------------
+    // ---- receiver solves, in the order receivers were saturated; in the serial order a
+    //      donor solved with the event follows (case 2) or stands alone (case 3) --------------
     int off = nH + nA, g = gH + gA;
     for (int e = 0; e < nev; ++e) {
-        if (L.evC[e] == 3) continue;
+        if (L.evC[e] != 3) {
         const int j = L.evJ[e];
         const int aj = L.colA[j];
         if (tid < aj && tid < S) { L.ry[tid] = (int16_t)select_in_bits(&L.elig[j * hs], hs, tid); L.rorg[tid] = (int16_t)j; }
@@ -550,6 +600,87 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
             off += nUp + nDn;
         }
         __syncthreads();
+        }
+        if (L.evDW[e] >= 0) {
+            // the donor's own solve: exact 1D over the rows it held at that moment
+            if (wid == 0) {
+                const int i = L.evI[e];
+                const int ai = compact_bits_wave(&L.elig[i * hs], hs, L.P[0]);
+                const int *R = L.P[1];
+                remaining_rows_wave(L.P[0], ai, L.evDbc[e], L.cNb[i], L.cNbd[i], L.evDub[e], L.P[1]);
+                const int w = L.evDW[e];
+                int u = 0, c = 0, st = 0;
+                for (int k = lane; k < sh; k += kWave) {
+                    const int s = R[w + k], t = y0 + k;
+                    u += s < t; c += s != t; st += s < t ? t - s : s - t;
+                }
+                u = wave_sum(u); c = wave_sum(c); st = wave_sum(st);
+                if (c > 0) emit_line_wave(A, R, w, y0, sh, u, (uint32_t)off, false, i);
+                if (lane == 0) {
+                    if (c > 0 && g <= (int)A.group_cap) A.goff[g] = (uint32_t)off;
+                    L.misc[M_CNT] = c;
+                    atomicAdd(&L.misc[M_STEPS], st);
+                }
+            }
+            __syncthreads();
+            const int c = L.misc[M_CNT];
+            if (c > 0) { ++g; off += c; }
+            __syncthreads();
+        }
+    }
+
+    // ---- serial order: donors still unsolved after the loop, in ascending x, over the tokens
+    //      they still hold; their excess stays in the reservoir ----------------------------------
+    if (serial) {
+        for (int x = x0 + wid; x < x1; x += kWaves) {
+            if (L.dsol[x]) continue;
+            const int ai = compact_bits_wave(&L.elig[x * hs], hs, Q);
+            const int bc = L.bcnt[x], ub = L.ubeg[x], nbd = L.cNbd[x];
+            const int ar = remaining_rows_wave(Q, ai, bc, L.cNb[x], nbd, ub, P);
+            const int w0 = e1d_window_wave(P, Q, ar, y0, sh);
+            int u = 0, c = 0, st = 0;
+            for (int k = lane; k < sh; k += kWave) {
+                const int s2 = P[w0 + k], t = y0 + k;
+                u += s2 < t; c += s2 != t; st += s2 < t ? t - s2 : s2 - t;
+            }
+            u = wave_sum(u); c = wave_sum(c); st = wave_sum(st);
+            if (lane == 0) {
+                if (w0 > bc || w0 + sh < bc + nbd) L.misc[M_ERR] = 1;
+                L.colW[x] = w0; L.colU[x] = u; L.colCnt[x] = c;
+                atomicAdd(&L.misc[M_STEPS], st);
+            }
+            wave_sync();
+        }
+        __syncthreads();
+        int nZ, gZ;
+        const int x = x0 + tid;
+        const bool last = x < x1 && !L.dsol[x];
+        const int cnt = last ? L.colCnt[x] : 0;
+        const int zoff = block_excl_scan(cnt, L.scanA, &nZ);
+        const int gi = block_excl_scan(cnt > 0 ? 1 : 0, L.scanB, &gZ);
+        if (cnt > 0) {
+            L.colOff[x] = off + zoff;
+            if (g + gi <= (int)A.group_cap) A.goff[g + gi] = (uint32_t)(off + zoff);
+        }
+        __syncthreads();
+        for (int x2 = x0 + wid; x2 < x1; x2 += kWaves) {
+            if (L.dsol[x2]) continue;
+            const int ai = compact_bits_wave(&L.elig[x2 * hs], hs, Q);
+            const int bc = L.bcnt[x2], ub = L.ubeg[x2];
+            remaining_rows_wave(Q, ai, bc, L.cNb[x2], L.cNbd[x2], ub, P);
+            const int w0 = L.colW[x2];
+            if (L.colCnt[x2] > 0)
+                emit_line_wave(A, P, w0, y0, sh, L.colU[x2], (uint32_t)L.colOff[x2], false, x2);
+            wave_sync();
+            if (lane == 0) {
+                // tokens left in the reservoir: those below and above the window
+                L.bcnt[x2] = w0;
+                L.ubeg[x2] = ub + (w0 + sh - bc - L.cNbd[x2]);
+            }
+        }
+        __syncthreads();
+        off += nZ;
+        g += gZ;
     }
 
     // ---- final grid: band full in central columns, parked tokens, remaining pools -----------
@@ -613,7 +744,7 @@ __global__ __launch_bounds__(kThreads) void k_solve_one(SolveArgs A)
 template <int S>
 __global__ __launch_bounds__(kThreads) void k_solve_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                          const uint64_t *occ, rr_move *mv, uint32_t *ga,
-                                                         uint64_t *fa, rr_solve_info *infos)
+                                                         uint64_t *fa, rr_solve_info *infos, uint32_t flags)
 {
     __shared__ SolveLds<S> L;
     const rr_desc d = desc[blockIdx.x];
@@ -629,6 +760,7 @@ __global__ __launch_bounds__(kThreads) void k_solve_many(const rr_desc *__restri
     }
     SolveArgs A;
     A.W = s.w; A.H = s.h; A.x0 = s.x0; A.y0 = s.y0; A.x1 = s.x1; A.y1 = s.y1;
+    A.flags = flags;
     A.occ = occ + d.occ_off;
     A.moves = mv + d.move_off;
     A.move_cap = d.move_cap;
@@ -650,17 +782,21 @@ static bool shape_valid(const rr_shape &s)
 
 extern "C" size_t rr_solve_workspace_bytes(rr_shape) { return 0; }
 
+static bool flags_valid(uint32_t flags) { return flags <= RR_REDREC_SERIAL; }
+
 extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *moves, uint32_t move_cap,
                               uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ,
-                              rr_solve_info *info, void *workspace, size_t workspace_bytes, void *stream)
+                              rr_solve_info *info, uint32_t flags, void *workspace, size_t workspace_bytes,
+                              void *stream)
 {
     (void)workspace; (void)workspace_bytes;
-    if (!shape_valid(shape)) return RR_E_INVAL;
+    if (!shape_valid(shape) || !flags_valid(flags)) return RR_E_INVAL;
     if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
     if (!occ || !group_off || !final_occ || !info || (move_cap > 0 && !moves)) return RR_E_INVAL;
     if (((uintptr_t)moves & 7u) != 0) return RR_E_INVAL;
     SolveArgs A;
     A.W = shape.w; A.H = shape.h; A.x0 = shape.x0; A.y0 = shape.y0; A.x1 = shape.x1; A.y1 = shape.y1;
+    A.flags = flags;
     A.occ = occ; A.moves = moves; A.move_cap = move_cap; A.goff = group_off; A.group_cap = group_cap;
     A.fin = final_occ; A.info = info;
     hipStream_t st = (hipStream_t)stream;
@@ -673,9 +809,12 @@ extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *move
 
 extern "C" rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
                                    const uint64_t *occ_arena, rr_move *move_arena, uint32_t *group_arena,
-                                   uint64_t *final_arena, rr_solve_info *infos, void *stream)
+                                   uint64_t *final_arena, rr_solve_info *infos, uint32_t flags, void *workspace,
+                                   size_t workspace_bytes, void *stream)
 {
+    (void)workspace; (void)workspace_bytes;
     if (n == 0) return RR_OK;
+    if (!flags_valid(flags)) return RR_E_INVAL;
     if (!desc || !occ_arena || !group_arena || !final_arena || !infos || !move_arena) return RR_E_INVAL;
     if (max_w < 1 || max_h < 1) return RR_E_INVAL;
     if (max_w > RR_MAX_SIDE || max_h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
@@ -684,13 +823,13 @@ extern "C" rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max
     const uint32_t side = max_w > max_h ? max_w : max_h;
     if (side <= 64)
         hipLaunchKernelGGL(k_solve_many<64>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
-                           occ_arena, move_arena, group_arena, final_arena, infos);
+                           occ_arena, move_arena, group_arena, final_arena, infos, flags);
     else if (side <= 128)
         hipLaunchKernelGGL(k_solve_many<128>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
-                           occ_arena, move_arena, group_arena, final_arena, infos);
+                           occ_arena, move_arena, group_arena, final_arena, infos, flags);
     else
         hipLaunchKernelGGL(k_solve_many<256>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
-                           occ_arena, move_arena, group_arena, final_arena, infos);
+                           occ_arena, move_arena, group_arena, final_arena, infos, flags);
     return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
 }
 

@@ -54,8 +54,9 @@ def _host_u32(t: torch.Tensor, n=None) -> np.ndarray:
 class SolveBuffers:
     """Device buffers of one rr_solve call (capacities default to the always-sufficient ones)."""
 
-    def __init__(self, shape, device="cuda", move_cap=None, group_cap=None):
+    def __init__(self, shape, device="cuda", move_cap=None, group_cap=None, flags=0):
         self.shape = tuple(int(v) for v in shape)
+        self.flags = int(flags)                  # order of Alg. 1 (RR_REDREC_*)
         mc, gc = solve_caps(shape)
         self.move_cap = mc if move_cap is None else int(move_cap)
         self.group_cap = gc if group_cap is None else int(group_cap)
@@ -73,7 +74,7 @@ class SolveBuffers:
 
     def run(self, stream=None):
         rr_solve(self.shape, self.occ, self.moves, self.move_cap, self.group_off, self.group_cap,
-                 self.final, self.info, None, 0, stream)
+                 self.final, self.info, self.flags, None, 0, stream)
         return self
 
     def host(self):
@@ -136,8 +137,9 @@ class ManyBuffers:
     Batching capacities are set by :meth:`plan_batches` from per-instance step counts (exact
     counts read back after the solve, or caller-chosen bounds)."""
 
-    def __init__(self, shapes, device="cuda"):
+    def __init__(self, shapes, device="cuda", solve_flags=0):
         self.device = device
+        self.solve_flags = int(solve_flags)      # order of Alg. 1 (RR_REDREC_*)
         self.n = len(shapes)
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         d = np.zeros(self.n, DESC_DTYPE)
@@ -174,7 +176,7 @@ class ManyBuffers:
 
     def solve(self, stream=None):
         rr_solve_many(self.n, self.desc, self.max_w, self.max_h, self.occ, self.moves, self.groups, self.final,
-                      self.sinfo, stream)
+                      self.sinfo, self.solve_flags, None, 0, stream)
         return self
 
     def solve_infos(self) -> np.ndarray:

@@ -182,7 +182,7 @@ class Server:
             c.occ.view(c.n, c.occ_words).index_copy_(0, idx, rows)
             w.sinfo = torch.empty(n * SOLVE_INFO_WORDS, dtype=torch.int32, device=self.device)
             w.binfo = torch.empty(n * BATCH_INFO_WORDS, dtype=torch.int32, device=self.device)
-            rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo, st)
+            rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo, 0, None, 0, st)
             rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, flags_for(c.side, self.flags),
                                 c.batches, c.steps,
                                 w.binfo, c.ws, c.ws.numel() * 8, st)

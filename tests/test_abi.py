@@ -51,19 +51,26 @@ def test_host_only_calls():
 
 @pytest.mark.parametrize("shape", [(0, 4, 0, 0, 1, 1), (4, 4, 2, 0, 2, 1), (4, 4, 0, 3, 4, 5), (4, 4, 0, 0, 5, 1)])
 def test_invalid_shapes_are_rejected_before_launch(shape):
-    rc = rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, None, 0, stream=0, check=False)
+    rc = rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, 0, None, 0, stream=0, check=False)
+    assert rc == rr.RR_E_INVAL
+
+
+def test_unknown_solve_order_is_rejected():
+    rc = rr.rr_solve((32, 32, 8, 8, 24, 24), 8, 8, 10, 8, 10, 8, 8, 2, None, 0, stream=0, check=False)
+    assert rc == rr.RR_E_INVAL
+    rc = rr.rr_solve_many(1, 8, 32, 32, 8, 8, 8, 8, 8, 7, None, 0, stream=0, check=False)
     assert rc == rr.RR_E_INVAL
 
 
 def test_oversized_grid_is_unsupported():
-    rc = rr.rr_solve((300, 300, 10, 10, 20, 20), 8, 8, 10, 8, 10, 8, 8, None, 0, stream=0, check=False)
+    rc = rr.rr_solve((300, 300, 10, 10, 20, 20), 8, 8, 10, 8, 10, 8, 8, 0, None, 0, stream=0, check=False)
     assert rc == rr.RR_E_UNSUPPORTED
 
 
 def test_null_outputs_and_small_workspace_rejected():
     shape = (32, 32, 8, 8, 24, 24)
-    assert rr.rr_solve(shape, 8, 8, 10, None, 10, 8, 8, None, 0, stream=0, check=False) == rr.RR_E_INVAL
-    assert rr.rr_solve(shape, 8, 12, 10, 8, 10, 8, 8, None, 0, stream=0, check=False) == rr.RR_E_INVAL  # misaligned
+    assert rr.rr_solve(shape, 8, 8, 10, None, 10, 8, 8, 0, None, 0, stream=0, check=False) == rr.RR_E_INVAL
+    assert rr.rr_solve(shape, 8, 12, 10, 8, 10, 8, 8, 0, None, 0, stream=0, check=False) == rr.RR_E_INVAL  # misaligned
     need = rr.rr_batch_workspace_bytes(shape, 100, 100)
     rc = rr.rr_batch_moves(shape, 8, 8, 8, 100, 0, 8, 100, 8, 100, 8, 8, need - 1, stream=0, check=False)
     assert rc == rr.RR_E_NOMEM
