@@ -102,14 +102,15 @@ def e1d_moves(p, b: int, t: int):
     return list(zip(src[:n].tolist(), dst[:n].tolist()))
 
 
-REDREC_PARALLEL, REDREC_SERIAL = 0, 1
+REDREC_PARALLEL, REDREC_SERIAL, BIRD = 0, 1, 2
 
 
-def solve(shape, occ, move_cap=None, group_cap=None, trace=False, serial=False):
+def solve(shape, occ, move_cap=None, group_cap=None, trace=False, serial=False, bird=False):
     """Run the oracle solve on packed rows ``occ`` (uint64[h][ws]).
 
     ``serial`` selects the serial order of Alg. 1 (donors solved after they donate) instead of
-    the parallel one of §III.D.  Returns a dict: rc, status, moves (uint16[n][4] = sx,sy,dx,dy),
+    the parallel one of §III.D; ``bird`` selects the bird algorithm (Alg. 2) instead of red-rec.
+    Returns a dict: rc, status, moves (uint16[n][4] = sx,sy,dx,dy),
     group_off (uint32[g+1]), final (uint64[h][ws]), n_steps, need_moves, need_groups and, with
     ``trace``, events."""
     sh = make_shape(shape)
@@ -124,11 +125,12 @@ def solve(shape, occ, move_cap=None, group_cap=None, trace=False, serial=False):
     final = np.zeros_like(occ)
     info = SolveInfo()
     out = {}
-    if trace or serial:
+    algo = BIRD if bird else (REDREC_SERIAL if serial else REDREC_PARALLEL)
+    if trace or algo:
         ev = (Event * (w + 1))()
         nev = C.c_uint32(0)
         rc = lib().rr_oracle_solve_trace(C.byref(sh), _ptr(occ), _ptr(moves), move_cap, _ptr(goff), group_cap,
-                                         _ptr(final), C.byref(info), REDREC_SERIAL if serial else REDREC_PARALLEL,
+                                         _ptr(final), C.byref(info), algo,
                                          C.cast(ev, C.c_void_p), w + 1, C.byref(nev))
         if trace:
             out["events"] = [(e.donor, e.receiver, e.kase, e.k_bottom, e.count)

@@ -32,7 +32,7 @@ enum { O_OK = 0, O_INFEASIBLE = 1, O_E_INVAL = -1, O_E_CAPACITY = -2, O_E_NOMEM 
 enum { O_LAMBDA_LINE_OR_COL = 0, O_LAMBDA_ALONG = 1, O_LAMBDA_NONE = 2 };
 /* Order of Alg. 1: the parallel form of §III.D (every non-negative column solved from the
  * outset; canonical) or the serial form of §III.C (donors solved after they donate). */
-enum { O_REDREC_PARALLEL = 0, O_REDREC_SERIAL = 1 };
+enum { O_REDREC_PARALLEL = 0, O_REDREC_SERIAL = 1, O_BIRD = 2 };
 
 typedef struct { uint16_t w, h, x0, y0, x1, y1; } o_shape;
 typedef struct { uint16_t sx, sy, dx, dy; } o_move;
@@ -204,6 +204,7 @@ typedef struct {
     int *up, *nu, *uh;         /* upper reservoir pool of column x, nearest-first; size; head */
     o_src *mk; int *nm;        /* tokens marked for receiver x (row, donor); count */
     int serial;                /* serial order of Alg. 1 (donors solved after they donate) */
+    int bird;                  /* bird (Alg. 2) instead of the donor/receiver loop */
     int *solved;               /* central column already solved (serial order) */
     int *dr;                   /* scratch rows of a donor solve */
     mlist L;
@@ -317,6 +318,63 @@ static int pair_better(const int *sp, int i, int j, int bi, int bj)
     return i < bi;
 }
 
+/* A token of the generalized 1-D instance of bird: virtual row v on the column being solved,
+ * tie order t among tokens of one virtual row, physical trap (x, y). */
+typedef struct { int v, t, x, y; } o_vtok;
+
+static int cmp_vtok(const void *a, const void *b)
+{
+    const o_vtok *p = (const o_vtok *)a, *q = (const o_vtok *)b;
+    if (p->v != q->v) return (p->v > q->v) - (p->v < q->v);
+    return (p->t > q->t) - (p->t < q->t);
+}
+
+/* bird (§III.E, Alg. 2) after the non-negative columns are solved: the columns of negative
+ * surplus, leftmost first, each filled by the generalized exact 1D.  For column j the line is
+ * column j itself; its own tokens stand at their rows, and every reservoir token of another
+ * column x stands at the row it would reach with the same Manhattan distance to the target of
+ * column j: y + |x - j| above the band, y - |x - j| below it (several tokens can share one
+ * virtual row; target rows of other columns are never taken).  The generalized exact 1D (the
+ * cheapest run of sh consecutive sorted virtual tokens, ties to the leftmost run) picks the
+ * tokens; among tokens of one virtual row the nearest column comes first, and on equal
+ * distance the left column (reading: the paper fixes only "the closest possible column"), so a
+ * run boundary inside a shared row keeps the nearest tokens.  A chosen token runs along its
+ * row to column j, then along the column; moves follow the exact-1D emission order. */
+static void bird(rr_state *S)
+{
+    const int W = S->W, H = S->H, x0 = S->x0, y0 = S->y0, x1 = S->x1, y1 = S->y1, sh = S->sh;
+    o_vtok *c = (o_vtok *)malloc(sizeof(o_vtok) * (size_t)W * H);
+    int *v = (int *)malloc(sizeof(int) * (size_t)W * H);
+    if (!c || !v) { free(c); free(v); S->L.oom = 1; return; }
+    for (int j = x0; j < x1; ++j) {
+        if (S->sigma[j] >= 0) continue;
+        int n = 0;
+        for (int x = 0; x < W; ++x)
+            for (int y = 0; y < H; ++y) {
+                if (!S->cell[y * W + x]) continue;
+                int band = (y >= y0 && y < y1);
+                if (x != j && band) continue;
+                int d = iabs(x - j), pr = 2 * d + (x > j);
+                c[n].x = x; c[n].y = y;
+                c[n].v = (x == j) ? y : (y >= y1 ? y + d : y - d);
+                c[n].t = (c[n].v >= y0) ? pr : -pr;     /* nearest first above, nearest last below */
+                n++;
+            }
+        if (n < sh) { S->status = O_E_INTERNAL; break; }
+        qsort(c, (size_t)n, sizeof(o_vtok), cmp_vtok);
+        for (int k = 0; k < n; ++k) v[k] = c[k].v;
+        int w = e1d_window(v, n, y0, sh);
+        size_t start = S->L.n;
+        for (int k = sh - 1; k >= 0; --k)                 /* towards larger rows, largest target first */
+            if (c[w + k].v < y0 + k) ml_push(&S->L, c[w + k].x, c[w + k].y, j, y0 + k);
+        for (int k = 0; k < sh; ++k)                      /* towards smaller rows, smallest target first */
+            if (c[w + k].v > y0 + k) ml_push(&S->L, c[w + k].x, c[w + k].y, j, y0 + k);
+        apply_moves(S->cell, W, &S->L, start);
+        ml_close_group(&S->L, start);
+    }
+    free(c); free(v);
+}
+
 static void redrec(rr_state *S)
 {
     const int W = S->W, H = S->H, x0 = S->x0, y0 = S->y0, x1 = S->x1, y1 = S->y1;
@@ -411,6 +469,8 @@ static void redrec(rr_state *S)
             for (int k = 0; k < a; ++k) if (qx[k] >= y1) S->up[x * H + S->nu[x]++] = qx[k];
         }
     }
+
+    if (S->bird) { bird(S); goto out; }
 
     /* Donor/receiver loop (Alg. 1 main loop, pairing rule of §III.C).  sp = pool size for a
      * solved column, the deficit for a receiver (negative), 0 once a column is settled. */
@@ -516,10 +576,11 @@ static int solve_impl(const o_shape *shape, const uint64_t *occ, o_move *moves, 
                       uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ, o_solve_info *info,
                       uint32_t flags, o_event *ev, uint32_t ev_cap, uint32_t *n_ev)
 {
-    if (!shape_ok(shape) || !occ || !info || flags > O_REDREC_SERIAL) return O_E_INVAL;
+    if (!shape_ok(shape) || !occ || !info || flags > O_BIRD) return O_E_INVAL;
     rr_state S;
     memset(&S, 0, sizeof S);
     S.serial = (flags == O_REDREC_SERIAL);
+    S.bird = (flags == O_BIRD);
     S.W = shape->w; S.H = shape->h;
     S.x0 = shape->x0; S.y0 = shape->y0; S.x1 = shape->x1; S.y1 = shape->y1;
     S.sw = S.x1 - S.x0; S.sh = S.y1 - S.y0;
@@ -601,7 +662,7 @@ int rr_oracle_solve(const o_shape *shape, const uint64_t *occ, o_move *moves, ui
 }
 
 /* Same solve, also reporting the donor/receiver loop's events in order; flags selects the
- * order of Alg. 1 (O_REDREC_PARALLEL or O_REDREC_SERIAL). */
+ * order of Alg. 1 (O_REDREC_PARALLEL or O_REDREC_SERIAL) or bird (O_BIRD, no events). */
 int rr_oracle_solve_trace(const o_shape *shape, const uint64_t *occ, o_move *moves, uint32_t move_cap,
                           uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ, o_solve_info *info,
                           uint32_t flags, o_event *events, uint32_t event_cap, uint32_t *n_events)
