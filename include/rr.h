@@ -89,6 +89,13 @@ typedef struct {
  * and in the order of the groups. */
 #define RR_REDREC_PARALLEL 0u
 #define RR_REDREC_SERIAL   1u
+/* bird (§III.E, Alg. 2) instead of red-rec, same flags field: after the row pre-pass and the
+ * columns of non-negative surplus (solved as in RR_REDREC_PARALLEL), each column of negative
+ * surplus, leftmost first, is filled by the generalized exact 1D from its own tokens and the
+ * reservoir tokens of every other column, a token at (x, y) standing at the virtual row
+ * y + |x - j| above the target or y - |x - j| below it; among tokens of one virtual row the
+ * nearest column comes first, then the left one.  One group per such column. */
+#define RR_BIRD            2u
 
 /* Largest grid side the device kernels take. */
 #define RR_MAX_SIDE 256u
@@ -108,7 +115,7 @@ size_t rr_solve_workspace_bytes(rr_shape shape);
  *                    surplus with moves, one per receiver column in the order it was saturated.
  *   final_occ  [out] bit rows of the grid after all moves (H*ws words).
  *   info       [out] one rr_solve_info.
- *   flags      [in]  RR_REDREC_PARALLEL or RR_REDREC_SERIAL (any other value: RR_E_INVAL).
+ *   flags      [in]  RR_REDREC_PARALLEL, RR_REDREC_SERIAL or RR_BIRD (any other value: RR_E_INVAL).
  * An instance is solved iff F = N - D - (x1-x0)*(y1-y0) >= 0, decided before any move: N is
  * the number of tokens and D the number of target-row tokens beyond the target width,
  * counted only when the target leaves side columns (the row pre-pass parks those tokens in
@@ -181,7 +188,7 @@ typedef struct {
 
 /* Solve n instances in one launch; instance i reads occ_arena + desc[i].occ_off and writes
  * moves/group offsets/final bit rows at its offsets and infos[i].  Results are bit-identical to
- * n calls of rr_solve with the same flags (the order of Alg. 1, as in rr_solve).  max_w / max_h
+ * n calls of rr_solve with the same flags (the algorithm, as in rr_solve).  max_w / max_h
  * bound every instance's grid (they pick the kernel variant; an instance beyond them gets
  * RR_E_INVAL).  workspace / workspace_bytes: n * rr_solve_workspace_bytes of the largest grid
  * (0 for grids up to RR_MAX_SIDE: NULL is then accepted). */

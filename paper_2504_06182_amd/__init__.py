@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "librr.so")
 RR_OK, RR_INFEASIBLE = 0, 1
 RR_E_INVAL, RR_E_CAPACITY, RR_E_DEVICE, RR_E_NOMEM, RR_E_INTERNAL, RR_E_UNSUPPORTED = -1, -2, -3, -4, -5, -6
 RR_LAMBDA_LINE_OR_COL, RR_LAMBDA_ALONG, RR_LAMBDA_NONE = 0, 1, 2
-RR_REDREC_PARALLEL, RR_REDREC_SERIAL = 0, 1
+RR_REDREC_PARALLEL, RR_REDREC_SERIAL, RR_BIRD = 0, 1, 2
 RR_BATCH_GENERIC = 1 << 16
 RR_MAX_SIDE = 256
 RR_NOALLOC_WORKSPACE_BYTES = 64 << 20

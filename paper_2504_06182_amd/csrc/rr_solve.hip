@@ -27,6 +27,7 @@ constexpr int kWaves = kThreads / kWave;
 enum { M_STEPS = 0, M_NEV = 1, M_ERR = 2, M_CNT = 3 };
 
 constexpr uint32_t kOrderSerial = 1u;   // RR_REDREC_SERIAL
+constexpr uint32_t kBird = 2u;          // RR_BIRD
 
 template <int S>
 struct SolveLds {
@@ -43,6 +44,9 @@ struct SolveLds {
     // donor solved with the event (serial order): window start over its remaining tokens, and
     // its remaining pool bounds at that moment ([0,bc) below, [ub,a) above); evDW < 0: none
     int16_t evDW[S + 1], evDbc[S + 1], evDub[S + 1];
+    // bird: histograms of reservoir tokens by virtual distance from the band (above: u = v - y1,
+    // below: u = y0 - 1 - v) and their exclusive prefix counts and sums of virtual rows
+    int hT[2 * S + 2], hB[2 * S + 2], cT[2 * S + 3], cB[2 * S + 3], sT[2 * S + 3], sB[2 * S + 3];
     int P[kWaves][S + 1];
     int Q[kWaves][S + 2];
     uint64_t rkey[S];
@@ -366,6 +370,231 @@ __device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
 }
 
 // ------------------------------------------------------------------------------------------
+// bird (§III.E, Alg. 2): the columns of negative surplus, leftmost first, each filled by the
+// generalized exact 1D.  For column j every reservoir token of another column x stands at the
+// virtual row y + |x - j| (above the band) or y - |x - j| (below): the row with the same
+// Manhattan distance to the target of column j; its own tokens stand at their rows.  The
+// cheapest run of sh sorted virtual tokens holds every own band token (exact-1D lemma), so it
+// is fixed by k, the tokens taken from below: the k nearest below, the band tokens and the
+// sh - band - k nearest above.  Among tokens of one virtual row the nearest column comes
+// first, then the left one.  L.cols holds the current grid, column by column.
+
+// Column x once settled: its band full (central) or its parked band tokens (side), plus, for a
+// donor, the pool left in its reservoir -- indices [0, bcnt) and [ubeg, a) of its sorted
+// eligible rows.
+template <int S>
+__device__ __forceinline__ void settle_column(SolveLds<S> &L, int x, int hs, int y0, int y1, bool central, bool donor)
+{
+    int keepLow = L.bcnt[x], dropLow = L.ubeg[x];
+    for (int sl = 0; sl < hs; ++sl) {
+        const uint64_t band = range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
+        uint64_t f = central ? band : (L.cols[x * hs + sl] & band);
+        if (donor) {
+            const uint64_t e = L.elig[x * hs + sl];
+            const int c = popc(e);
+            uint64_t lowPart;
+            if (keepLow >= c) lowPart = e;
+            else lowPart = keepLow > 0 ? (e & low_mask(select_bit(e, keepLow))) : 0ull;
+            uint64_t dropPart;
+            if (dropLow >= c) dropPart = e;
+            else dropPart = dropLow > 0 ? (e & low_mask(select_bit(e, dropLow))) : 0ull;
+            f |= lowPart | (e & ~dropPart);
+            keepLow = keepLow > c ? keepLow - c : 0;
+            dropLow = dropLow > c ? dropLow - c : 0;
+        }
+        L.cols[x * hs + sl] = f;
+    }
+}
+
+// tokens of column x in rows below y
+__device__ __forceinline__ int popc_below(const uint64_t *cols, int hs, int x, int y)
+{
+    int c = 0;
+    for (int sl = 0; sl < hs; ++sl) c += popc(cols[x * hs + sl] & low_mask(y - 64 * sl));
+    return c;
+}
+
+__device__ __forceinline__ bool col_bit(const uint64_t *cols, int hs, int x, int y)
+{
+    return (cols[x * hs + (y >> 6)] >> (y & 63)) & 1ull;
+}
+
+// rank among the tokens of one virtual row (nearest column first, then left): occupied traps of
+// that row's diagonal closer to column j, and the left trap at the same distance for a right one
+__device__ __forceinline__ int diag_rank(const uint64_t *cols, int hs, int W, int H, int j, int x, int y, bool above)
+{
+    const int d = x > j ? x - j : j - x;
+    const int v = above ? y + d : y - d;
+    int q = 0;
+    for (int e = 0; e < d; ++e) {
+        const int r = above ? v - e : v + e;
+        if (r < 0 || r >= H) continue;
+        if (e == 0) { q += col_bit(cols, hs, j, r); continue; }
+        if (j - e >= 0) q += col_bit(cols, hs, j - e, r);
+        if (j + e < W) q += col_bit(cols, hs, j + e, r);
+    }
+    if (x > j && j - d >= 0) q += col_bit(cols, hs, j - d, y);
+    return q;
+}
+
+template <int S>
+__device__ void bird_columns(SolveLds<S> &L, const SolveArgs &A, int &off, int &g)
+{
+    const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
+    const int W = A.W, H = A.H, x0 = A.x0, y0 = A.y0, x1 = A.x1, y1 = A.y1, sh = y1 - y0;
+    const int hs = (H + 63) >> 6;
+    const int nT = H - y1 + W, nBl = y0 + W;        // histogram lengths above / below
+    for (int j = x0; j < x1; ++j) {
+        if (L.sig[j] >= 0) continue;
+        for (int u = tid; u < 2 * S + 2; u += kThreads) { L.hT[u] = 0; L.hB[u] = 0; }
+        __syncthreads();
+        // pass 1: every reservoir token (own ones too) by virtual distance from the band
+        for (int p = tid; p < W * hs; p += kThreads) {
+            const int x = p / hs, sl = p - x * hs;
+            const int d = x > j ? x - j : j - x;
+            uint64_t c = L.cols[p] & ~range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
+            while (c) {
+                const int b = __ffsll((unsigned long long)c) - 1;
+                c &= c - 1;
+                const int y = 64 * sl + b;
+                if (y >= y1) atomicAdd(&L.hT[y + d - y1], 1);
+                else atomicAdd(&L.hB[y0 - 1 - (y - d)], 1);
+            }
+        }
+        __syncthreads();
+        if (wid == 0) {
+            // exclusive prefix counts and sums of virtual rows, above and below
+            int carryC = 0, carryS = 0;
+            for (int base = 0; base < nT; base += kWave) {
+                const int u = base + lane;
+                const int c = u < nT ? L.hT[u] : 0, sv = c * (y1 + u);
+                const int ic = wave_incl_scan(c), is = wave_incl_scan(sv);
+                if (u < nT) { L.cT[u + 1] = carryC + ic; L.sT[u + 1] = carryS + is; }
+                carryC += __shfl(ic, kWave - 1, kWave); carryS += __shfl(is, kWave - 1, kWave);
+            }
+            carryC = 0; carryS = 0;
+            for (int base = 0; base < nBl; base += kWave) {
+                const int u = base + lane;
+                const int c = u < nBl ? L.hB[u] : 0, sv = c * (y0 - 1 - u);
+                const int ic = wave_incl_scan(c), is = wave_incl_scan(sv);
+                if (u < nBl) { L.cB[u + 1] = carryC + ic; L.sB[u + 1] = carryS + is; }
+                carryC += __shfl(ic, kWave - 1, kWave); carryS += __shfl(is, kWave - 1, kWave);
+            }
+            if (lane == 0) { L.cT[0] = 0; L.sT[0] = 0; L.cB[0] = 0; L.sB[0] = 0; }
+            wave_sync();
+            // own band tokens: E[m] = r_m - y0 - m over their sorted rows, and prefix sums
+            int *P0 = L.P[0], *E = L.P[1], *EQ = L.Q[1];
+            const int aj = compact_bits_wave(&L.cols[j * hs], hs, P0);
+            int nb0 = 0;
+            for (int sl = 0; sl < hs; ++sl) nb0 += popc(L.cols[j * hs + sl] & low_mask(y0 - 64 * sl));
+            int nbd = 0;
+            for (int sl = 0; sl < hs; ++sl) nbd += popc(L.cols[j * hs + sl] & range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl));
+            (void)aj;
+            for (int m = lane; m < nbd; m += kWave) E[m] = P0[nb0 + m] - y0 - m;
+            wave_sync();
+            prefix_sums_wave(E, nbd, EQ);
+            const int NT = L.cT[nT], NB = L.cB[nBl], need = sh - nbd;
+            const int klo = need - NT > 0 ? need - NT : 0, khi = need < NB ? need : NB;
+            uint64_t best = ~0ull;
+            for (int k = klo + lane; k <= khi; k += kWave) {
+                // k nearest below onto y0.., band tokens onto y0+k.., need-k nearest above
+                int lo = 0, hi = nBl;                   // last u with cB[u] <= k
+                while (lo < hi) { const int mid = (lo + hi + 1) >> 1; if (L.cB[mid] <= k) lo = mid; else hi = mid - 1; }
+                const long sumB = L.sB[lo] + (long)(k - L.cB[lo]) * (y0 - 1 - lo);
+                const int nt = need - k;
+                lo = 0; hi = nT;
+                while (lo < hi) { const int mid = (lo + hi + 1) >> 1; if (L.cT[mid] <= nt) lo = mid; else hi = mid - 1; }
+                const long sumT = L.sT[lo] + (long)(nt - L.cT[lo]) * (y1 + lo);
+                const long cb = (long)k * y0 + (long)k * (k - 1) / 2 - sumB;
+                const long ct = sumT - ((long)nt * y1 - (long)nt * (nt + 1) / 2);
+                int a = 0, b = nbd;
+                while (a < b) { const int mid = (a + b) >> 1; if (E[mid] < k) a = mid + 1; else b = mid; }
+                const long cband = (long)k * a - EQ[a] + (EQ[nbd] - EQ[a]) - (long)k * (nbd - a);
+                const uint64_t key = ((uint64_t)(cb + cband + ct) << 16) | (uint64_t)(0xFFFF - k);
+                best = key < best ? key : best;
+            }
+            best = wave_min_u64(best);
+            if (best == ~0ull && lane == 0) L.misc[M_ERR] = 1;
+            const int k = 0xFFFF - (int)(best & 0xFFFFull);
+            if (lane == 0) { L.misc[4] = k; L.misc[5] = nb0; L.misc[6] = nbd; }
+        }
+        __syncthreads();
+        const int k = L.misc[4], nb0 = L.misc[5], nbd = L.misc[6];
+        const int nt = sh - nbd - k;
+        // boundaries: the virtual distance where the k-th (nt-th) nearest token lies, and how
+        // many tokens of that virtual row are taken
+        int uB = 0, uT = 0;
+        {
+            int lo = 0, hi = nBl;
+            while (lo < hi) { const int mid = (lo + hi + 1) >> 1; if (L.cB[mid] <= k) lo = mid; else hi = mid - 1; }
+            uB = lo;
+            lo = 0; hi = nT;
+            while (lo < hi) { const int mid = (lo + hi + 1) >> 1; if (L.cT[mid] <= nt) lo = mid; else hi = mid - 1; }
+            uT = lo;
+        }
+        const int qB = k - L.cB[uB], qT = nt - L.cT[uT];
+        // pass 2: chosen tokens and their targets (sorted virtual order onto y0, y0+1, ...)
+        for (int p = tid; p < W * hs; p += kThreads) {
+            const int x = p / hs, sl = p - x * hs;
+            uint64_t c = L.cols[p];
+            if (x != j) c &= ~range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
+            while (c) {
+                const int b = __ffsll((unsigned long long)c) - 1;
+                c &= c - 1;
+                const int y = 64 * sl + b;
+                const int d = x > j ? x - j : j - x;
+                int t = -1;
+                if (y >= y1) {
+                    const int u = y + d - y1;
+                    if (u < uT || (u == uT && qT > 0)) {
+                        const int q = diag_rank(L.cols, hs, W, H, j, x, y, true);
+                        if (u < uT || q < qT) t = y0 + k + nbd + L.cT[u] + q;
+                    }
+                } else if (y < y0) {
+                    const int u = y0 - 1 - (y - d);
+                    if (u < uB || (u == uB && qB > 0)) {
+                        const int q = diag_rank(L.cols, hs, W, H, j, x, y, false);
+                        if (u < uB || q < qB) t = y0 + k - 1 - L.cB[u] - q;
+                    }
+                } else {
+                    t = y0 + k + popc_below(L.cols, hs, j, y) - nb0;
+                }
+                if (t >= y0 && t < y1) { L.ry[t - y0] = (int16_t)y; L.rorg[t - y0] = (int16_t)x; }
+                else if (t != -1) L.misc[M_ERR] = 1;
+            }
+        }
+        __syncthreads();
+        // emission: movers towards larger rows by target descending, then towards smaller rows
+        // by target ascending
+        int up = 0, dn = 0, x = j, y = 0, t = y0 + tid;
+        if (tid < sh) {
+            y = L.ry[tid]; x = L.rorg[tid];
+            const bool moving = (x != j) || (y != t);
+            const bool isUp = (x == j) ? (y < t) : (y < y0);
+            up = moving && isUp;
+            dn = moving && !isUp;
+        }
+        int nUp, nDn;
+        const int upEx = block_excl_scan(up, L.scanA, &nUp);
+        const int dnEx = block_excl_scan(dn, L.scanB, &nDn);
+        if (up) put_move(A, (uint32_t)(off + nUp - (upEx + 1)), x, y, j, t);
+        if (dn) put_move(A, (uint32_t)(off + nUp + dnEx), x, y, j, t);
+        int st = (up || dn) ? ((x > j ? x - j : j - x) + (t > y ? t - y : y - t)) : 0;
+        st = wave_sum(st);
+        if (lane == 0 && st) atomicAdd(&L.misc[M_STEPS], st);
+        if (up || dn) atomicAnd((unsigned long long *)&L.cols[x * hs + (y >> 6)], ~(1ull << (y & 63)));
+        if (nUp + nDn > 0) {
+            if (tid == 0 && g <= (int)A.group_cap) A.goff[g] = (uint32_t)off;
+            ++g;
+            off += nUp + nDn;
+        }
+        __syncthreads();
+        if (tid < hs) L.cols[j * hs + tid] |= range_mask(y0 - 64 * tid, y1 - 1 - 64 * tid);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 
 template <int S>
 __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
@@ -376,6 +605,7 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     const int ws = (W + 63) >> 6, hs = (H + 63) >> 6;
     const bool side = (x0 > 0 || x1 < W);
     const bool serial = (A.flags & 0xFFu) == kOrderSerial;
+    const bool birdAlg = (A.flags & 0xFFu) == kBird;
     int *P = L.P[wid];
     int *Q = L.Q[wid];
 
@@ -532,6 +762,14 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     }
     __syncthreads();
 
+    int off = nH + nA, g = gH + gA;
+    if (birdAlg) {
+        // ---- bird: the grid after the non-negative columns (band full, their excess where it
+        //      stood), then the negative columns leftmost first ----------------------------------
+        if (tid < W && tid >= x0 && tid < x1 && L.sig[tid] >= 0) settle_column<S>(L, tid, hs, y0, y1, true, true);
+        __syncthreads();
+        bird_columns<S>(L, A, off, g);
+    } else {
     // ---- donor/receiver pairs ---------------------------------------------------------------
     if (wid == 0) pair_loop<S>(L, W, hs, y0, y1, sh);
     __syncthreads();
@@ -539,7 +777,6 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
 
     // ---- receiver solves, in the order receivers were saturated; in the serial order a
     //      donor solved with the event follows (case 2) or stands alone (case 3) --------------
-    int off = nH + nA, g = gH + gA;
     for (int e = 0; e < nev; ++e) {
         if (L.evC[e] != 3) {
         const int j = L.evJ[e];
@@ -685,30 +922,11 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
 
     // ---- final grid: band full in central columns, parked tokens, remaining pools -----------
     if (tid < W) {
-        const int x = tid;
-        const bool central = (x >= x0 && x < x1);
-        const bool donor = !central || L.sig[x] >= 0;
-        int keepLow = L.bcnt[x], dropLow = L.ubeg[x];   // pool left: indices [0,bcnt) and [ubeg,a)
-        for (int sl = 0; sl < hs; ++sl) {
-            const uint64_t band = range_mask(y0 - 64 * sl, y1 - 1 - 64 * sl);
-            uint64_t f = central ? band : (L.cols[x * hs + sl] & band);
-            if (donor) {
-                const uint64_t e = L.elig[x * hs + sl];
-                const int c = popc(e);
-                uint64_t lowPart;
-                if (keepLow >= c) lowPart = e;
-                else lowPart = keepLow > 0 ? (e & low_mask(select_bit(e, keepLow))) : 0ull;
-                uint64_t dropPart;
-                if (dropLow >= c) dropPart = e;
-                else dropPart = dropLow > 0 ? (e & low_mask(select_bit(e, dropLow))) : 0ull;
-                f |= lowPart | (e & ~dropPart);
-                keepLow = keepLow > c ? keepLow - c : 0;
-                dropLow = dropLow > c ? dropLow - c : 0;
-            }
-            L.cols[x * hs + sl] = f;
-        }
+        const bool central = (tid >= x0 && tid < x1);
+        settle_column<S>(L, tid, hs, y0, y1, central, !central || L.sig[tid] >= 0);
     }
     __syncthreads();
+    }
     for (int p = wid; p < H * ws; p += kWaves) {
         const int y = p / ws, j = p - y * ws;
         const int x = 64 * j + lane;
@@ -782,7 +1000,7 @@ static bool shape_valid(const rr_shape &s)
 
 extern "C" size_t rr_solve_workspace_bytes(rr_shape) { return 0; }
 
-static bool flags_valid(uint32_t flags) { return flags <= RR_REDREC_SERIAL; }
+static bool flags_valid(uint32_t flags) { return flags <= RR_BIRD; }
 
 extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *moves, uint32_t move_cap,
                               uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ,

@@ -56,7 +56,7 @@ def test_invalid_shapes_are_rejected_before_launch(shape):
 
 
 def test_unknown_solve_order_is_rejected():
-    rc = rr.rr_solve((32, 32, 8, 8, 24, 24), 8, 8, 10, 8, 10, 8, 8, 2, None, 0, stream=0, check=False)
+    rc = rr.rr_solve((32, 32, 8, 8, 24, 24), 8, 8, 10, 8, 10, 8, 8, 3, None, 0, stream=0, check=False)
     assert rc == rr.RR_E_INVAL
     rc = rr.rr_solve_many(1, 8, 32, 32, 8, 8, 8, 8, 8, 7, None, 0, stream=0, check=False)
     assert rc == rr.RR_E_INVAL

@@ -1,6 +1,7 @@
-"""GPU parity of the serial order of Alg. 1 (RR_REDREC_SERIAL), through the C ABI, against the
-oracle's serial order, bit for bit: moves, group offsets, final grids, step counts, and the
-batches of the serial solve's moves.  Every case prints its name before it touches the GPU."""
+"""GPU parity of the solver variants, through the C ABI, against the oracle's same variant, bit
+for bit: the serial order of Alg. 1 (RR_REDREC_SERIAL) and bird (Alg. 2, RR_BIRD).  Moves, group
+offsets, final grids, step counts, and the batches of the variant's moves.  Every case prints
+its name before it touches the GPU."""
 import glob
 import json
 import os
@@ -17,7 +18,13 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-SERIAL = 1          # RR_REDREC_SERIAL
+SERIAL, BIRD = 1, 2          # RR_REDREC_SERIAL, RR_BIRD
+VARIANTS = [SERIAL, BIRD]
+NAMES = {SERIAL: "serial", BIRD: "bird"}
+
+
+def oracle_solve(shape, occ, algo):
+    return oracle.solve(shape, occ, serial=(algo == SERIAL), bird=(algo == BIRD))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -53,7 +60,7 @@ def same_batch(g, r, tag=""):
         assert np.array_equal(g["steps"], r["steps"]), tag
 
 
-def gpu_solve(shape, occ, flags=SERIAL):
+def gpu_solve(shape, occ, flags):
     from paper_2504_06182_amd.pipeline import SolveBuffers
     sb = SolveBuffers(shape, flags=flags).load(occ).run()
     torch.cuda.synchronize()
@@ -67,9 +74,9 @@ def gpu_batch(sb, n_steps, flags=0):
     return bb.host()
 
 
-def check_one(shape, occ, tag, batch_flags=(0,)):
-    sb, g = gpu_solve(shape, occ)
-    r = oracle.solve(shape, occ, serial=True)
+def check_one(shape, occ, tag, algo, batch_flags=(0,)):
+    sb, g = gpu_solve(shape, occ, algo)
+    r = oracle_solve(shape, occ, algo)
     same_solve(g, r, tag)
     if r["status"] == 0:
         check_solve(shape, occ, g)
@@ -110,31 +117,39 @@ ADVERSARIAL = [
 ]
 
 
+@pytest.mark.parametrize("algo", VARIANTS, ids=[NAMES[a] for a in VARIANTS])
 @pytest.mark.parametrize("name,shape,fn", ADVERSARIAL, ids=[a[0] for a in ADVERSARIAL])
-def test_serial_adversarial(name, shape, fn):
-    say("case serial", name, shape)
+def test_variant_adversarial(name, shape, fn, algo):
+    say("case", NAMES[algo], name, shape)
     occ = ri.pack_rows(dense(shape[0], shape[1], fn))
-    check_one(shape, occ, name, batch_flags=(0,) if shape[0] * shape[1] > 130 * 130 else (0, 1, 2))
+    check_one(shape, occ, name, algo, batch_flags=(0,) if shape[0] * shape[1] > 130 * 130 else (0, 1, 2))
 
 
-@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(os.path.dirname(__file__), "golden", "serial",
-                                                               "*.json"))))
-def test_serial_fixtures_on_gpu(path):
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+FIXTURES = ([(p, (("serial", SERIAL), ("parallel", 0))) for p in sorted(glob.glob(os.path.join(GOLDEN, "serial", "*.json")))]
+            + [(p, (("bird", BIRD), ("redrec", 0))) for p in sorted(glob.glob(os.path.join(GOLDEN, "bird", "*.json")))])
+
+
+@pytest.mark.parametrize("path,orders", FIXTURES, ids=[os.path.basename(f[0]) for f in FIXTURES])
+def test_variant_fixtures_on_gpu(path, orders):
+    """The hand-worked fixtures of both variants: groups and step counts of the variant and of
+    the default red-rec, as worked out by hand."""
     g = json.load(open(path))
     shape = tuple(g["shape"])
-    say("case serial fixture", os.path.basename(path))
+    say("case fixture", os.path.basename(path))
     d = np.zeros((shape[1], shape[0]), np.uint8)
     for x, y in g["tokens"]:
         d[y, x] = 1
-    for order, flags in (("serial", SERIAL), ("parallel", 0)):
+    for order, flags in orders:
         _, r = gpu_solve(shape, ri.pack_rows(d), flags)
         goff = r["group_off"]
         groups = [[list(map(int, m)) for m in r["moves"][goff[k]:goff[k + 1]]] for k in range(len(goff) - 1)]
         assert groups == g[order]["groups"] and r["n_steps"] == g[order]["n_steps"], order
 
 
+@pytest.mark.parametrize("algo", VARIANTS, ids=[NAMES[a] for a in VARIANTS])
 @pytest.mark.parametrize("seed", range(16))
-def test_serial_random_shapes(seed):
+def test_variant_random_shapes(seed, algo):
     rng = np.random.default_rng(1000 + seed)
     w, h = int(rng.integers(1, 200)), int(rng.integers(2, 200))
     sw, sh = int(rng.integers(1, w + 1)), int(rng.integers(1, h))
@@ -143,42 +158,44 @@ def test_serial_random_shapes(seed):
         x0, sw = 0, w                             # full-width band
     shape = (w, h, x0, y0, x0 + sw, y0 + sh)
     p = float(rng.choice([0.5, 0.6, 0.7, 0.8]))
-    say("case serial random", seed, shape, p)
+    say("case", NAMES[algo], "random", seed, shape, p)
     occ = ri.pack_rows(ri.bernoulli_grid(901, seed, w, h, p))
-    check_one(shape, occ, f"seed {seed}", batch_flags=(seed % 3,) if w * h <= 120 * 120 else ())
+    check_one(shape, occ, f"seed {seed}", algo, batch_flags=(seed % 3,) if w * h <= 120 * 120 else ())
 
 
+@pytest.mark.parametrize("algo", VARIANTS, ids=[NAMES[a] for a in VARIANTS])
 @pytest.mark.parametrize("name", ["single32", "single128", "paper32"])
-def test_serial_single_workloads(name):
+def test_variant_single_workloads(name, algo):
     d = ri.config_shots(name)[0]
     shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
-    say("case serial", name, shape)
-    check_one(shape, ri.shot_grid(d), name, batch_flags=(0, 1, 2))
+    say("case", NAMES[algo], name, shape)
+    check_one(shape, ri.shot_grid(d), name, algo, batch_flags=(0, 1, 2))
 
 
-def test_serial_many_instances_batch64_and_mixed():
-    """Serial solves of 1024 shots of the 64 x 64 workload and 48 uneven shots in
-    many-instance launches: 24 sampled 64 x 64 shots and every uneven shot equal the oracle's
-    serial order, every uneven shot equals its one-instance launch; batching of the sampled
-    shots equals the oracle's."""
+@pytest.mark.parametrize("algo", VARIANTS, ids=[NAMES[a] for a in VARIANTS])
+def test_variant_many_instances_batch64_and_mixed(algo):
+    """The variant on 1024 shots of the 64 x 64 workload and 48 uneven shots in many-instance
+    launches: 24 sampled 64 x 64 shots and every uneven shot equal the oracle's same variant,
+    every uneven shot equals its one-instance launch; batching of the sampled shots equals the
+    oracle's."""
     from paper_2504_06182_amd.pipeline import ManyBuffers
     for name, n, sample in (("batch64", 1024, 24), ("mixed", 48, 48)):
         shots = ri.config_shots(name, n=n)
         shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
         grids = [ri.shot_grid(d) for d in shots]
-        say("case serial many", name, n)
-        mb = ManyBuffers(shapes, solve_flags=SERIAL).load(grids).solve()
+        say("case", NAMES[algo], "many", name, n)
+        mb = ManyBuffers(shapes, solve_flags=algo).load(grids).solve()
         torch.cuda.synchronize()
         sinf = mb.solve_infos()
         mb.plan_batches([max(int(i[3]), 1) for i in sinf]).batch(0)
         torch.cuda.synchronize()
         binf = mb.batch_infos()
         for i in np.linspace(0, n - 1, sample).astype(int):
-            r = oracle.solve(shapes[i], grids[i], serial=True)
+            r = oracle_solve(shapes[i], grids[i], algo)
             g = mb.host_solve(i, sinf)
             same_solve(g, r, f"{name} {i}")
             if name == "mixed":
-                _, g1 = gpu_solve(shapes[i], grids[i])
+                _, g1 = gpu_solve(shapes[i], grids[i], algo)
                 same_solve(g1, r, f"{name} single {i}")
             if r["status"] == 0 and shapes[i][0] <= 128:
                 rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], indexed=True)
