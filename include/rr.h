@@ -234,6 +234,32 @@ rr_status rr_plan_many(uint32_t n, rr_desc *desc, const rr_solve_info *infos, ui
                        uint64_t batch_pool, uint64_t ws_pool_bytes, uint64_t *totals, void *stream);
 
 /* ------------------------------------------------------------------------------------------ */
+/* Exact 1D on chains                                                                           */
+
+/* Longest chain rr_solve_chains takes (move coordinates are 16-bit). */
+#define RR_MAX_CHAIN 65535u
+
+/* Bytes of device workspace rr_solve_chains needs for n chains of at most max_len traps: 0 up
+ * to 8192 traps (token positions stay in LDS), else n * 8 * (max_len + 2). */
+size_t rr_solve_chains_workspace_bytes(uint32_t n, uint32_t max_len);
+
+/* Exact 1D on n independent chains of traps in one launch (§III.A: distance-minimising
+ * assignment of tokens to a contiguous target and moves along the chain; its parallel form,
+ * §III.B).  A chain is a 1 x N grid: desc[i].shape = {N, 1, b, 0, b + t, 1} with 1 <= N <=
+ * max_len <= RR_MAX_CHAIN and target [b, b+t); its bit row, moves, group offsets (one group, or
+ * none when nothing moves) and final bit row go to the arenas at desc[i]'s offsets as in
+ * rr_solve_many.  A chain with fewer tokens than targets gives RR_INFEASIBLE (no move, final =
+ * input); a malformed shape gives RR_E_INVAL in infos[i].  The matching is the cheapest run of
+ * t consecutive tokens onto [b, b+t) (ties: the leftmost run); moves towards larger positions
+ * come first, largest target first, then the others, smallest target first.  For N up to
+ * RR_MAX_SIDE the results are byte for byte those of rr_solve on the same 1 x N grid.
+ * move_cap >= t always suffices.  workspace: rr_solve_chains_workspace_bytes(n, max_len) bytes
+ * (NULL when that is 0). */
+rr_status rr_solve_chains(uint32_t n, const rr_desc *desc, uint32_t max_len, const uint64_t *occ_arena,
+                          rr_move *move_arena, uint32_t *group_arena, uint64_t *final_arena,
+                          rr_solve_info *infos, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------------------------ */
 /* Batching with no allocation                                                                 */
 
 /* Size of the library's own batching workspace: one file-scope device array per GPU, held from

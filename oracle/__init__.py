@@ -176,3 +176,30 @@ def batch(shape, moves, group_off, n_steps, status=OK, flags=LAMBDA_LINE_OR_COL,
         out["batch_off"] = boff[:bi.n_batches + 1].copy()
         out["steps"] = steps[:bi.n_steps].copy()
     return out
+
+
+def solve_chain(n: int, occ_row, b: int, t: int):
+    """Exact 1D on a chain of n traps (a 1 x n grid; bit row ``occ_row``) with the contiguous
+    target [b, b+t): the exact-1D window and emission of §III.A (``rr_oracle_e1d_moves``) over
+    the sorted token positions.  Returns the layout of :func:`solve` for that 1 x n grid:
+    status, moves (uint16[k][4], rows 0), group_off (one group, or none), final, n_steps."""
+    row = np.ascontiguousarray(occ_row, dtype=np.uint64).reshape(-1)
+    bits = np.unpackbits(row.view(np.uint8), bitorder="little")[:n]
+    p = np.nonzero(bits)[0].astype(np.int32)
+    if len(p) < t:
+        return dict(status=INFEASIBLE, moves=np.zeros((0, 4), np.uint16), group_off=np.zeros(1, np.uint32),
+                    final=row.reshape(1, -1).copy(), n_steps=0)
+    pairs = e1d_moves(p, b, t)
+    moves = np.zeros((len(pairs), 4), np.uint16)
+    for k, (s, d) in enumerate(pairs):
+        moves[k] = (s, 0, d, 0)
+    w = e1d_window(p, b, t)
+    fin = bits.copy()
+    fin[p[w:w + t]] = 0
+    fin[b:b + t] = 1
+    padded = np.zeros(row.size * 64, np.uint8)
+    padded[:n] = fin
+    final = np.packbits(padded, bitorder="little").view(np.uint64).reshape(1, -1)
+    goff = np.array([0, len(pairs)] if pairs else [0], np.uint32)
+    steps = int(sum(abs(int(s) - int(d)) for s, d in pairs))
+    return dict(status=OK, moves=moves, group_off=goff, final=final, n_steps=steps)

@@ -19,6 +19,7 @@ RR_LAMBDA_LINE_OR_COL, RR_LAMBDA_ALONG, RR_LAMBDA_NONE = 0, 1, 2
 RR_REDREC_PARALLEL, RR_REDREC_SERIAL, RR_BIRD = 0, 1, 2
 RR_BATCH_GENERIC = 1 << 16
 RR_MAX_SIDE = 256
+RR_MAX_CHAIN = 65535
 RR_NOALLOC_WORKSPACE_BYTES = 64 << 20
 STATUS_NAMES = {0: "RR_OK", 1: "RR_INFEASIBLE", -1: "RR_E_INVAL", -2: "RR_E_CAPACITY", -3: "RR_E_DEVICE",
                 -4: "RR_E_NOMEM", -5: "RR_E_INTERNAL", -6: "RR_E_UNSUPPORTED"}
@@ -65,6 +66,8 @@ _SIGS = {
     "rr_batch_workspace_bytes": ([rr_shape, _U32, _U32], _SZ),
     "rr_batch_moves": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P, _SZ, _P], C.c_int),
     "rr_batch_moves_noalloc": ([rr_shape, _P, _P, _P, _U32, _U32, _P, _U32, _P, _U32, _P, _P], C.c_int),
+    "rr_solve_chains_workspace_bytes": ([_U32, _U32], _SZ),
+    "rr_solve_chains": ([_U32, _P, _U32, _P, _P, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "rr_solve_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _P, _P, _U32, _P, _SZ, _P], C.c_int),
     "rr_batch_moves_many": ([_U32, _P, _U32, _U32, _P, _P, _P, _U32, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "rr_plan_many": ([_U32, _P, _P, C.c_uint64, C.c_uint64, C.c_uint64, _P, _P], C.c_int),
@@ -153,6 +156,18 @@ def rr_batch_moves_noalloc(shape, moves, group_off, sinfo, move_cap, flags, batc
                                       int(flags), _ptr(batch_off), int(batch_cap), _ptr(steps), int(step_cap),
                                       _ptr(binfo), _stream(stream))
     return _check(rc, "rr_batch_moves_noalloc") if check else rc
+
+
+def rr_solve_chains_workspace_bytes(n: int, max_len: int) -> int:
+    return int(lib().rr_solve_chains_workspace_bytes(int(n), int(max_len)))
+
+
+def rr_solve_chains(n, desc, max_len, occ_arena, move_arena, group_arena, final_arena, infos, workspace=None,
+                    workspace_bytes=0, stream=None, check=True) -> int:
+    rc = lib().rr_solve_chains(int(n), _ptr(desc), int(max_len), _ptr(occ_arena), _ptr(move_arena),
+                               _ptr(group_arena), _ptr(final_arena), _ptr(infos), _ptr(workspace),
+                               int(workspace_bytes), _stream(stream))
+    return _check(rc, "rr_solve_chains") if check else rc
 
 
 def rr_solve_many(n, desc, max_w, max_h, occ_arena, move_arena, group_arena, final_arena, infos,

@@ -7,7 +7,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rr_solve.hip", "rr_batch.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rr_solve.hip", "rr_batch.hip", "rr_chain.hip")]
 HEADERS = [os.path.join(HERE, "csrc", h) for h in ("rr_device.hpp", "rr_batch_generic.hpp", "rr_batch_graph.hpp",
                                                    "rr_batch_loop.hpp")] + [os.path.join(ROOT, "include", "rr.h")]
 LIB = os.path.join(HERE, "librr.so")

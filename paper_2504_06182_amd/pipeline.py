@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_moves_many_staged, rr_batch_workspace_bytes,
-               rr_plan_many, rr_solve, rr_solve_many)
+               rr_plan_many, rr_solve, rr_solve_chains, rr_solve_chains_workspace_bytes, rr_solve_many)
 from .tune import flags_for
 
 SOLVE_INFO_WORDS = 6   # rr_solve_info: int32 status + 5 x uint32
@@ -271,6 +271,23 @@ class ManyBuffers:
             out["steps"] = steps[so:so + out["n_steps"]].copy()
             out["batch_off"] = batches[bo:bo + out["n_batches"] + 1].copy()
         return out
+
+
+class ChainBuffers(ManyBuffers):
+    """Arenas for rr_solve_chains: chains given as (N, b, t) -- N traps, target [b, b+t) -- laid
+    out as 1 x N grids (same arenas, descriptors and readback as ManyBuffers)."""
+
+    def __init__(self, chains, device="cuda", max_len=None):
+        shapes = [(int(n), 1, int(b), 0, int(b) + int(t), 1) for n, b, t in chains]
+        super().__init__(shapes, device=device)
+        self.max_len = int(max_len) if max_len is not None else self.max_w
+        self.chain_ws_bytes = rr_solve_chains_workspace_bytes(self.n, self.max_len)
+        self.chain_ws = _dev((self.chain_ws_bytes + 7) // 8, torch.int64, device) if self.chain_ws_bytes else None
+
+    def solve(self, stream=None):
+        rr_solve_chains(self.n, self.desc, self.max_len, self.occ, self.moves, self.groups, self.final, self.sinfo,
+                        self.chain_ws, self.chain_ws_bytes, stream)
+        return self
 
 
 # ------------------------------------------------------------------------------------------

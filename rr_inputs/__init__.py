@@ -108,6 +108,12 @@ CONFIGS = {
     # the paper's benchmark geometry: N_tx = 32 columns, N_ty = ceil(N_tx / 0.6) = 54 rows, a
     # full-width 32 x 32 target (centre-compact), exactly floor(0.6 * 32 * 54) = 1036 atoms
     "paper32": dict(n=1000, w=32, h=54, sw=32, sh=32, count=1036, seed=6),
+    # the paper's chain geometry: a centre-compact target of N_t / 2 traps in a chain of N_t
+    # traps, exactly floor(0.6 * N_t) atoms; N_t = 1024 as timed there, and the longest chain
+    # the move format holds (coordinates are 16-bit); chains are 1 x N grids (x < 2**24 keeps
+    # cell keys distinct)
+    "chain1024": dict(n=1000, w=1024, h=1, sw=512, sh=1, count=614, seed=7),
+    "chain65535": dict(n=16, w=65535, h=1, sw=32767, sh=1, count=39321, seed=8),
 }
 
 
@@ -117,7 +123,7 @@ def config_shots(name: str, n: int | None = None, first: int = 0):
     total = c["n"] if n is None else n
     shots = []
     for i in range(first, first + total):
-        if name == "paper32":
+        if "count" in c:
             x0, y0, x1, y1 = centred_target(c["w"], c["h"], c["sw"], c["sh"])
             shots.append(dict(w=c["w"], h=c["h"], x0=x0, y0=y0, x1=x1, y1=y1, p=None, count=c["count"],
                               seed=c["seed"], shot=i))
