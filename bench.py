@@ -8,10 +8,13 @@ Workload: 8192 shots of a 64x64 trap grid loaded i.i.d. Bernoulli(0.55), centred
 
 Reported in one JSON line: batched shots/s (value), the roofline of the dominant kernel, and
 the other forms of the same path: one shot per launch (rr_solve + rr_batch_moves) with p50/p99
-latency; the paper's own benchmark geometry, per launch and batched; the uneven-size batch as
-one graph-captured chain per size class; a served Poisson stream with continuous batching
-(p50/p99 overall and per class).  The CPU leg, run before the GPU is touched, times the oracle
-on the host cores and computes the oracle results the bit-exact samples are checked against.
+latency; the single-instance 32 x 32 and 128 x 128 configurations on the one-instance path;
+the paper's own benchmark geometry, per launch and batched; the uneven-size batch as one
+graph-captured chain per size class; a served Poisson stream with continuous batching (p50/p99
+overall and per class); the serial order of red-rec and bird on the batched workload; exact 1D
+on chains in the paper's 1-D geometry.  The CPU leg, run before the GPU is touched, times the
+oracle on the host cores and computes the oracle results the bit-exact samples are checked
+against.
 """
 from __future__ import annotations
 
@@ -69,8 +72,10 @@ def cpu_baseline(seconds: float, max_workers: int):
 
 def oracle_references(verify_shots: int, paper_shots: int, flags: int):
     """Part of the CPU baseline leg, run before the GPU is touched: the oracle's solve and batching
-    results for the sampled shots of the 8192-shot workload and of the paper's geometry whose GPU
-    results the run checks bit for bit afterwards."""
+    results for the sampled shots of the 8192-shot workload, of the paper's geometry and of the
+    two single-instance configurations whose GPU results the run checks bit for bit afterwards,
+    the oracle's chain results for a sample of the paper's chain geometry, and the pair-loop
+    iterations of the sampled 64 x 64 shots (a dependency floor of the solve)."""
     import numpy as np
 
     import oracle
@@ -78,16 +83,22 @@ def oracle_references(verify_shots: int, paper_shots: int, flags: int):
     oracle.build()
     refs = {}
     for name, idx in ((WORKLOAD, np.linspace(0, 8191, verify_shots).astype(int) if verify_shots > 0 else []),
-                      ("paper32", range(min(8, paper_shots)))):
+                      ("paper32", range(min(8, paper_shots))), ("single32", [0]), ("single128", [0])):
         out = {}
         for i in idx:
             d = ri.config_shots(name, n=1, first=int(i))[0]
             shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
-            r = oracle.solve(shape, ri.shot_grid(d))
-            rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF) \
+            r = oracle.solve(shape, ri.shot_grid(d), trace=True)
+            rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags & 0xFF, indexed=True) \
                 if r["status"] == 0 else None
             out[int(i)] = (r, rb)
         refs[name] = out
+    refs["pair_loop_iterations"] = [len(r["events"]) for r, _ in refs[WORKLOAD].values()]
+    chains = {}
+    for i in range(8):
+        d = ri.config_shots("chain1024", n=1, first=i)[0]
+        chains[i] = oracle.solve_chain(d["w"], ri.shot_grid(d)[0], d["x0"], d["x1"] - d["x0"])
+    refs["chain1024"] = chains
     return refs
 
 
@@ -264,6 +275,173 @@ def paper_geometry_form(args, dev, n_single, refs):
                               "note": "mean time per instance over 1000 instances; batching not timed there"}}
 
 
+def _same(g, r):
+    import numpy as np
+    ok = g["status"] == r["status"] and np.array_equal(np.asarray(g["final"]).reshape(-1),
+                                                        np.asarray(r["final"]).reshape(-1))
+    if ok and r["status"] == 0:
+        ok = np.array_equal(g["moves"], r["moves"]) and np.array_equal(g["group_off"], r["group_off"])
+    return ok
+
+
+def single_instance_form(args, dev, refs):
+    """The two single-instance configurations (32 x 32 grid, p 0.5, centred 16 x 16 target; 128 x
+    128, p 0.6, centred 90 x 90), each on the plain one-instance path: --single-launches
+    synchronised launches of rr_solve, and of rr_solve + rr_batch_moves (host clock, p50/p99),
+    plus the device time of each kernel chain from HIP events."""
+    import numpy as np
+    import torch
+
+    import rr_inputs as ri
+    from paper_2504_06182_amd.pipeline import BatchBuffers, SolveBuffers
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name in ("single32", "single128"):
+        d = ri.config_shots(name)[0]
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        sb = SolveBuffers(shape, device=dev).load(ri.shot_grid(d))
+        sb.run(stream)
+        torch.cuda.synchronize()
+        g = sb.host()
+        bb = BatchBuffers(sb, step_cap=max(g["n_steps"], 1), device=dev)
+        for _ in range(5):
+            sb.run(stream); bb.run(args.flags, stream)
+        torch.cuda.synchronize()
+        lat_s, lat_b, dev_s, dev_b = [], [], [], []
+        for _ in range(args.single_launches):
+            a = time.perf_counter()
+            sb.run(stream)
+            torch.cuda.synchronize()
+            lat_s.append((time.perf_counter() - a) * 1e6)
+        for _ in range(args.single_launches):
+            a = time.perf_counter()
+            sb.run(stream)
+            bb.run(args.flags, stream)
+            torch.cuda.synchronize()
+            lat_b.append((time.perf_counter() - a) * 1e6)
+        for _ in range(20):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream); sb.run(stream); e[1].record(stream); bb.run(args.flags, stream); e[2].record(stream)
+            torch.cuda.synchronize()
+            dev_s.append(e[0].elapsed_time(e[1]) * 1e3); dev_b.append(e[1].elapsed_time(e[2]) * 1e3)
+        exact = None
+        if name in refs:
+            r, rb = refs[name][0]
+            gb = bb.host()
+            exact = bool(_same(sb.host(), r) and (rb is None or (np.array_equal(gb["steps"], rb["steps"])
+                                                                and np.array_equal(gb["batch_off"], rb["batch_off"]))))
+        out[name] = {"grid": [d["w"], d["h"]], "target": [d["x1"] - d["x0"], d["y1"] - d["y0"]], "p": d["p"],
+                     "moves": g["n_moves"], "steps": g["n_steps"], "batches": bb.host()["n_batches"],
+                     "solve_p50_us": round(float(np.percentile(lat_s, 50)), 1),
+                     "solve_p99_us": round(float(np.percentile(lat_s, 99)), 1),
+                     "solve_batch_p50_us": round(float(np.percentile(lat_b, 50)), 1),
+                     "solve_batch_p99_us": round(float(np.percentile(lat_b, 99)), 1),
+                     "device_solve_us": round(float(np.median(dev_s)), 1),
+                     "device_batch_us": round(float(np.median(dev_b)), 1),
+                     "launches": args.single_launches, "bit_exact": exact}
+    return out
+
+
+def variants_form(args, dev):
+    """The solver variants on the 8192-shot 64 x 64 workload, each as a batched step (solve ->
+    plan -> batch): red-rec in the parallel order of §III.D (the default), red-rec in the serial
+    order of Alg. 1, and bird (Alg. 2); device times from HIP events (median of 3) and the mean
+    moves, unit steps and batches per shot (the operational side: fewer steps, fewer batches)."""
+    import numpy as np
+    import torch
+
+    import rr_inputs as ri
+    import paper_2504_06182_amd as rr
+    from paper_2504_06182_amd.pipeline import ManyBuffers
+    from paper_2504_06182_amd.tune import flags_for
+    shots = ri.config_shots(WORKLOAD)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    stream = torch.cuda.current_stream()
+    bflags = flags_for(64, args.flags)
+    ws_one = rr.rr_batch_workspace_bytes(shapes[0], 2 * 44 * 44, STEP_BOUND_PER_SHOT)
+    out = {}
+    for name, algo in (("redrec_parallel", 0), ("redrec_serial", 1), ("bird", 2)):
+        mb = ManyBuffers(shapes, device=dev, solve_flags=algo).load(grids)
+        n = mb.n
+        mb.alloc_pools(n * STEP_BOUND_PER_SHOT, n * (STEP_BOUND_PER_SHOT + 1), n * ((ws_one + 255) // 256 * 256))
+        ts, tb = [], []
+        for rep in range(4):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream); mb.solve(stream); e[1].record(stream)
+            mb.plan_device(stream); mb.batch(bflags, stream); e[2].record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                ts.append(e[0].elapsed_time(e[1])); tb.append(e[1].elapsed_time(e[2]))
+        sinf, binf = mb.solve_infos(), mb.batch_infos()
+        ok = sinf[:, 0].view(np.int32) == 0
+        assert np.all(binf[:, 0].view(np.int32) == 0)
+        out[name] = {"solve_ms": round(float(np.median(ts)), 3), "plan_batch_ms": round(float(np.median(tb)), 3),
+                     "shots_per_s": round(n / ((np.median(ts) + np.median(tb)) / 1e3), 1),
+                     "mean_moves": round(float(sinf[ok, 1].mean()), 1), "mean_steps": round(float(sinf[ok, 3].mean()), 1),
+                     "mean_batches": round(float(binf[ok, 1].mean()), 1)}
+        del mb
+    return out
+
+
+def chain_form(args, dev, refs):
+    """Exact 1D on chains (§III.A-B) in the paper's chain geometry: 1024 traps, centre-compact
+    target of 512, exactly 614 atoms (1000 chains).  One chain per synchronised launch (host
+    clock p50/p99; the paper: 22 us on one CPU core for the serial form), all 1000 in one launch
+    (device time per chain), and 16 chains of 65535 traps in one launch."""
+    import numpy as np
+    import torch
+
+    import rr_inputs as ri
+    from paper_2504_06182_amd.pipeline import ChainBuffers
+    stream = torch.cuda.current_stream()
+    shots = ri.config_shots("chain1024")
+    chains = [(d["w"], d["x0"], d["x1"] - d["x0"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    one = [ChainBuffers([chains[i]], device=dev).load([grids[i]]) for i in range(args.single_launches)]
+    for cb in one[:5]:
+        cb.solve(stream)
+    torch.cuda.synchronize()
+    lat = []
+    for cb in one:
+        a = time.perf_counter()
+        cb.solve(stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e6)
+    allc = ChainBuffers(chains, device=dev).load(grids)
+
+    def timed(cb, reps=5):
+        ts = []
+        for _ in range(reps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            e[0].record(stream); cb.solve(stream); e[1].record(stream)
+            torch.cuda.synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+        return float(np.median(ts[1:]))
+
+    t_all = timed(allc)
+    sinf = allc.solve_infos()
+    exact = None
+    if "chain1024" in refs:
+        exact = sum(int(_same(allc.host_solve(i, sinf), r)) for i, r in refs["chain1024"].items())
+        exact = f"{exact}/{len(refs['chain1024'])}"
+    long_shots = ri.config_shots("chain65535")
+    longc = ChainBuffers([(d["w"], d["x0"], d["x1"] - d["x0"]) for d in long_shots], device=dev)
+    longc.load([ri.shot_grid(d) for d in long_shots])
+    t_long = timed(longc)
+    return {"workload": "chains of 1024 traps, centre-compact target of 512, exactly 614 atoms placed uniformly "
+                        "(the paper's 1-D geometry), 1000 chains",
+            "per_launch_p50_us": round(float(np.percentile(lat, 50)), 1),
+            "per_launch_p99_us": round(float(np.percentile(lat, 99)), 1), "per_launch_sample": len(lat),
+            "batched_launch_ms": round(t_all, 3), "batched_us_per_chain": round(t_all * 1e3 / len(chains), 4),
+            "mean_moves": round(float(sinf[:, 1].mean()), 1), "mean_steps": round(float(sinf[:, 3].mean()), 1),
+            "bit_exact_sample": exact or "not checked (--no-cpu)",
+            "long_chains": {"chains": len(long_shots), "traps": 65535, "target": 32767, "atoms": 39321,
+                            "launch_ms": round(t_long, 3)},
+            "paper_context": {"exact_1d_serial_cpu_us_at_1024": 22,
+                              "hardware": "AMD Threadripper 2950X (CPU); the paper's GPU form stops at 1024 traps"}}
+
+
 def served_form(args, dev):
     """Served stream: Poisson arrivals at --serve-rate shots/s for --serve-seconds of the uneven
     mix (grid side uniform over {32..256}), fed to the continuous-batching server; per-shot
@@ -320,6 +498,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--serve-budget-gib", type=int, default=176)
     ap.add_argument("--serve-max-wave", type=int, default=1024)
+    ap.add_argument("--single-launches", type=int, default=200,
+                    help="synchronised launches per single-instance configuration and chain (0: skip those forms)")
+    ap.add_argument("--no-variants", action="store_true", help="skip the serial-order and bird forms")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the timed region, run one plain device copy of this many MiB (a known-size "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
@@ -451,6 +632,9 @@ def main():
     per_launch_sps = len(per) / (tp1 - tp0)
     lat = np.array(lat)
 
+    single = single_instance_form(args, dev, refs) if args.single_launches > 0 else None
+    chains = chain_form(args, dev, refs) if args.single_launches > 0 else None
+    variants = variants_form(args, dev) if not args.no_variants else None
     paper = paper_geometry_form(args, dev, args.paper_shots, refs.get("paper32")) if args.paper_shots > 0 else None
     mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
     served = served_form(args, dev) if args.serve_seconds > 0 else None
@@ -491,11 +675,13 @@ def main():
                   "per_launch_p99_us": round(float(np.percentile(lat, 99)), 1),
                   "per_launch_sample": len(lat),
                   "batched_step_latency_us": round(ms_per_step * 1e3, 1),
-                  "paper_geometry": paper, "mixed_graph": mixed,
-                  "served": served},
+                  "single_instance": single, "paper_geometry": paper, "mixed_graph": mixed,
+                  "served": served, "variants": variants, "chains": chains},
         "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
                            "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),
-                           "mean_batches": round(float(n_batches.mean()), 1)},
+                           "mean_batches": round(float(n_batches.mean()), 1),
+                           "mean_pair_loop_iterations": (round(float(np.mean(refs["pair_loop_iterations"])), 1)
+                                                         if refs.get("pair_loop_iterations") else None)},
         "bit_exact_sample": f"{exact}/{len(ref64)}" if ref64 else "not checked (--no-cpu)",
         "cpu_baseline": cpu,
     }
