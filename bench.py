@@ -102,7 +102,8 @@ def oracle_references(verify_shots: int, paper_shots: int, flags: int):
     return refs
 
 
-BATCH_SOURCES = ("rr_batch.hip", "rr_batch_graph.hpp", "rr_batch_loop.hpp", "rr_batch_generic.hpp", "rr_device.hpp")
+BATCH_SOURCES = ("rr_batch.hip", "rr_batch_graph.hpp", "rr_batch_loop.hpp", "rr_batch_generic.hpp", "rr_device.hpp",
+                 "rr_batch_common.hpp", "rr_batch_loop_kernels.hpp", "rr_batch_loop3.hip")
 PROFILE = os.path.join(ROOT, "profiles", "k_loop_many_batch64.md")
 
 

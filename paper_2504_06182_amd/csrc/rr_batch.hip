@@ -16,7 +16,7 @@
 #include "rr.h"
 #include "rr_batch_generic.hpp"
 #include "rr_batch_graph.hpp"
-#include "rr_batch_loop.hpp"
+#include "rr_batch_common.hpp"
 
 #include <atomic>
 #include <mutex>
@@ -25,50 +25,6 @@ static_assert(sizeof(rr_desc) == 80, "rr_desc layout");
 static_assert(sizeof(rr_move) == 8, "rr_move layout");
 
 namespace rr {
-
-constexpr uint32_t kFlagGeneric = 1u << 16;
-
-// shape check of a many-instance descriptor
-__device__ __forceinline__ bool shape_usable(const rr_shape s, int maxw, int maxh)
-{
-    return s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= RR_MAX_SIDE && s.h <= RR_MAX_SIDE &&
-           s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
-}
-
-// the instance's workspace region [ws_off, ws_off + layout total) is 256-byte aligned and lies
-// inside the workspace
-__device__ __forceinline__ bool ws_fits(const rr_desc &d, uint64_t ws_bytes)
-{
-    const uint64_t need = fast::layout(d.shape.w, d.shape.h, d.move_cap, d.step_cap).total;
-    return (d.ws_off & 255u) == 0 && d.ws_off <= ws_bytes && need <= ws_bytes - d.ws_off;
-}
-
-// a descriptor the kernels may run: valid shape, room found by the planner, workspace in bounds
-__device__ __forceinline__ bool desc_usable(const rr_desc &d, int maxw, int maxh, uint64_t ws_bytes)
-{
-    return shape_usable(d.shape, maxw, maxh) && d.step_cap != 0xFFFFFFFFu && ws_fits(d, ws_bytes);
-}
-
-__device__ __forceinline__ fast::Inst inst_of(const rr_desc &d, uint32_t i, const rr_move *mv, const uint32_t *ga,
-                                              const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
-                                              rr_batch_info *binfos, uint8_t *ws)
-{
-    fast::Inst I;
-    I.W = d.shape.w; I.H = d.shape.h;
-    I.moves = mv + d.move_off;
-    I.goff = ga + d.group_off;
-    I.sinfo = sinfos + i;
-    I.move_cap = d.move_cap;
-    I.step_cap = d.step_cap;
-    I.batch_cap = d.batch_cap;
-    I.boff = bat + d.batch_off;
-    I.steps = stp + d.step_off;
-    I.binfo = binfos + i;
-    I.ws = ws + d.ws_off;
-    return I;
-}
-
-extern __shared__ __attribute__((aligned(16))) uint8_t dyn_lds[];
 
 // ---- graph kernels
 
@@ -107,37 +63,11 @@ __global__ __launch_bounds__(fast::kGT) void k_graph_many(const rr_desc *__restr
                       (flags & kFlagGeneric) != 0);
 }
 
-// ---- loop kernels
+// ---- loop kernels: instantiated in rr_batch_loop3/5/8.hip
 
-template <int S, uint32_t F>
-__device__ __forceinline__ void loop_entry(const fast::Inst &I, uint32_t lds_bytes)
-{
-    const fast::Layout L = fast::layout(I.W, I.H, I.move_cap, I.step_cap);
-    uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
-    if (hdr[fast::H_STATE] != fast::ST_FAST) return;
-    // a ready set that outgrows the registers hands the instance to the general path
-    if (fast::loop_fast<S, F>(I, dyn_lds, lds_bytes) && lane_id() == 0) hdr[fast::H_STATE] = fast::ST_GENERIC;
-}
-
-// S register slots, F the local constraint (a compile-time constant: one kernel per constraint)
-template <int S, uint32_t F>
-__global__ __launch_bounds__(kWave) void k_loop_one(fast::Inst I, uint32_t lds_bytes)
-{
-    loop_entry<S, F>(I, lds_bytes);
-}
-
-template <int S, uint32_t F>
-__global__ __launch_bounds__(kWave) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
-                                                     const rr_move *mv, const uint32_t *ga,
-                                                     const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
-                                                     rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,
-                                                     uint32_t lds_bytes)
-{
-    const uint32_t i = blockIdx.x;
-    const rr_desc d = desc[i];
-    if (!desc_usable(d, maxw, maxh, ws_bytes)) return;
-    loop_entry<S, F>(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), lds_bytes);
-}
+RR_LOOP_KERNELS(extern, 3)
+RR_LOOP_KERNELS(extern, 5)
+RR_LOOP_KERNELS(extern, 8)
 
 // ---- general path
 

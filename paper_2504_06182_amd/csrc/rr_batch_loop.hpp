@@ -550,16 +550,22 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
     }
     (void)any_slow;
     if (!ok) { X.err = kOverflow; return; }
-    // keep the set in slot 0 while it fits there, so that trips stay on the one-slot path
+    // keep the set in as few slots as it fits (1; with 5 or more slots also 2; with 8, 4) so
+    // that trips scan only those
     if (S > 1) {
         uint32_t total = 0;
-        uint64_t high = 0;
+        uint64_t h1 = 0, h2 = 0, h4 = 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             total += (uint32_t)popc(R.vm[s]);
-            if (s > 0) high |= R.vm[s];
+            if (s >= 1) h1 |= R.vm[s];
+            if (s >= 2) h2 |= R.vm[s];
+            if (s >= 4) h4 |= R.vm[s];
         }
-        if (high && total <= (uint32_t)kWave) { compact(R, M.scratch); moved = true; }
+        const bool c1 = h1 && total <= (uint32_t)kWave;
+        const bool c2 = S >= 5 && h2 && total <= 2u * kWave;
+        const bool c4 = S >= 8 && h4 && total <= 4u * kWave;
+        if (c1 || c2 || c4) { compact(R, M.scratch); moved = true; }
     }
     if (ldone || moved) find_leader(R, X.ls, X.ll, X.lc, X.le, X.ln, X.lk);
 }
@@ -610,10 +616,19 @@ __device__ __forceinline__ bool loop_run(const Inst &I, const LoopMem &M, uint32
 
     while (X.alive > 0) {
         if (X.nb >= T || X.ls < 0) { X.err = kBroken; break; }   // every batch holds a step: at most T
-        uint64_t high = 0;
+        // trips scan only the slots that can hold entries: 1, 2 or 4 of them when the higher
+        // ones are empty (2 and 4 only for the larger register sets, whose ready sets often
+        // span a few slots), else all S
+        uint64_t h1 = 0, h2 = 0, h4 = 0;
 #pragma unroll
-        for (int s = 1; s < S; ++s) high |= R.vm[s];
-        if (!high) trip<1, S, flags>(R, X, I, M);
+        for (int s = 1; s < S; ++s) {
+            h1 |= R.vm[s];
+            if (s >= 2) h2 |= R.vm[s];
+            if (s >= 4) h4 |= R.vm[s];
+        }
+        if (!h1) trip<1, S, flags>(R, X, I, M);
+        else if (S >= 5 && !h2) trip<(S >= 5 ? 2 : S), S, flags>(R, X, I, M);
+        else if (S >= 8 && !h4) trip<(S >= 8 ? 4 : S), S, flags>(R, X, I, M);
         else trip<S, S, flags>(R, X, I, M);
         if (X.err) break;
     }
