@@ -443,18 +443,21 @@ def chain_form(args, dev, refs):
                               "hardware": "AMD Threadripper 2950X (CPU); the paper's GPU form stops at 1024 traps"}}
 
 
-def served_form(args, dev):
-    """Served stream: Poisson arrivals at --serve-rate shots/s for --serve-seconds of the uneven
+def served_form(args, dev, rate):
+    """Served stream: Poisson arrivals at ``rate`` shots/s for --serve-seconds of the uneven
     mix (grid side uniform over {32..256}), fed to the continuous-batching server; per-shot
     latency = completion seen by the host - arrival."""
+    import gc
+
     import numpy as np
+    import torch
 
     import rr_inputs as ri
     from paper_2504_06182_amd.serve import Server, poisson_arrivals, serve_stream
     pool = ri.config_shots("mixed", n=args.serve_pool)
     shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in pool]
     grids = [ri.shot_grid(d) for d in pool]
-    arrivals = poisson_arrivals(args.serve_rate, args.serve_seconds, seed=50)
+    arrivals = poisson_arrivals(rate, args.serve_seconds, seed=50)
     order = np.arange(len(arrivals)) % len(pool)
     srv = Server(budget_bytes=args.serve_budget_gib << 30, max_wave=args.serve_max_wave, flags=args.flags)
     warm = Server(budget_bytes=2 << 30, class_share={64: 0.2, 128: 0.3, 256: 0.5}, flags=args.flags)
@@ -470,13 +473,17 @@ def served_form(args, dev):
         if l_.size:
             per[str(side)] = {"n": int(l_.size), "p50_us": round(float(np.percentile(l_, 50)), 1),
                               "p99_us": round(float(np.percentile(l_, 99)), 1)}
-    return {"served_shots_per_s": round(len(arrivals) / wall, 1), "offered_rate": args.serve_rate,
+    out = {"served_shots_per_s": round(len(arrivals) / wall, 1), "offered_rate": rate,
             "shots": int(len(arrivals)), "p50_us": round(float(np.percentile(lat, 50)), 1),
             "p99_us": round(float(np.percentile(lat, 99)), 1), "per_class": per, "waves": srv.waves,
             "rerun_alone": srv.overflow, "slots": {str(k): v for k, v in srv.slots().items()},
-            "workload": f"Poisson arrivals at {args.serve_rate:g}/s for {args.serve_seconds:g} s, shots cycling "
+            "workload": f"Poisson arrivals at {rate:g}/s for {args.serve_seconds:g} s, shots cycling "
                         f"through {len(pool)} shots of the uneven mix; continuous batching, "
-                        f"{args.serve_budget_gib} GiB of slot arenas"}
+                        f"{args.serve_budget_gib} GiB of slot arenas, streams per class {srv.STREAMS}"}
+    del srv
+    gc.collect()                                     # the server's arenas go before the next one
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -495,7 +502,8 @@ def main():
     ap.add_argument("--paper-shots", type=int, default=200,
                     help="shots of the paper's geometry timed one launch at a time (0: skip the form)")
     ap.add_argument("--serve-seconds", type=float, default=10.0, help="served stream length (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-rates", type=str, default="20000,10000",
+                    help="offered rates of the served stream, one run each (shots/s, comma separated)")
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--serve-budget-gib", type=int, default=176)
     ap.add_argument("--serve-max-wave", type=int, default=1024)
@@ -638,7 +646,11 @@ def main():
     variants = variants_form(args, dev) if not args.no_variants else None
     paper = paper_geometry_form(args, dev, args.paper_shots, refs.get("paper32")) if args.paper_shots > 0 else None
     mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
-    served = served_form(args, dev) if args.serve_seconds > 0 else None
+    served = None
+    if args.serve_seconds > 0:
+        runs = [served_form(args, dev, float(r)) for r in args.serve_rates.split(",") if r.strip()]
+        served = dict(runs[0])
+        served["other_rates"] = runs[1:]
 
     value = n / (ms_per_step / 1e3)
     achieved = bytes_batch / (k_loop / 1e3) / 1e9

@@ -10,12 +10,14 @@ then one ``rr_solve_many`` + ``rr_batch_moves_many`` pair runs over just those s
 has several streams and a wave is launched only on a stream of its class that is idle, so while
 the class's streams are busy, arrivals gather into the next, larger wave (a wave takes every
 waiting shot its free slots and ``max_wave`` allow); waves of all classes overlap on the device.
-A wave retires when its completion event has fired: its shots are stamped done and their slots
-return to the free list.
+A wave retires when its completion event has fired: its infos were copied into pinned host
+memory on its own stream, so the host reads them without waiting on the device; its shots are
+stamped done and their slots return to the free list.
 
 Every result is that of a single ``rr_solve`` + ``rr_batch_moves`` on the same shot: the kernels
 work per instance and are deterministic, and a slot is sized so that the shot fits (a shot whose
-step count exceeds its slot's bound is re-run alone with exact buffers, and counted).
+step count exceeds its slot's bound is re-run alone with exact buffers on a stream of its own,
+retired by its event like a wave, and counted).
 
 Nothing here computes any part of the method: it schedules, copies and launches.
 """
@@ -43,13 +45,13 @@ def step_bound(side: int) -> int:
 class _Class:
     """Slot arenas of one size class (largest grid side ``side``)."""
 
-    def __init__(self, side, n_slots, n_streams, device):
+    def __init__(self, side, n_slots, n_streams, device, step_cap=None):
         self.side = side
         self.n = n_slots
         full = (side, side, 0, 0, side, side)
         self.occ_words = side * words_per_row(side)
         self.move_cap, self.group_cap = solve_caps(full)
-        self.step_cap = step_bound(side)
+        self.step_cap = step_bound(side) if step_cap is None else int(step_cap)
         self.ws_bytes = (rr_batch_workspace_bytes(full, self.move_cap, self.step_cap) + 255) // 256 * 256
         n = n_slots
         self.occ = torch.zeros(n * self.occ_words, dtype=torch.int64, device=device)
@@ -71,10 +73,10 @@ class _Class:
         return None
 
     @staticmethod
-    def slot_bytes(side):
+    def slot_bytes(side, step_cap=None):
         full = (side, side, 0, 0, side, side)
         mc, gc = solve_caps(full)
-        sc = step_bound(side)
+        sc = step_bound(side) if step_cap is None else int(step_cap)
         return (16 * side * words_per_row(side) + 8 * mc + 4 * (gc + 1) + 8 * sc + 4 +
                 rr_batch_workspace_bytes(full, mc, sc) + 256)
 
@@ -88,22 +90,35 @@ class Server:
 
     ``budget_bytes``: device memory for all arenas, split over the size classes by ``class_share``
     (fractions; a class's slot count is its share over its slot size).  ``max_wave``: most shots
-    one wave takes.  ``streams_per_class``: waves of one class in flight at once.  ``flags``:
-    batching flags.  ``keep_results``: copy every shot's outputs to the host when its wave retires
-    (for checking; off when only timing)."""
+    one wave takes.  ``streams_per_class``: waves of one class in flight at once (one number, or
+    one per class).  ``flags``: batching flags.  ``keep_results``: copy every shot's outputs to
+    the host when its wave retires (for checking; off when only timing).  ``slot_steps``: steps a
+    slot holds, per class (default step_bound)."""
 
-    def __init__(self, budget_bytes, class_share=None, max_wave=256, streams_per_class=4, flags=0,
-                 keep_results=False, device="cuda"):
+    # streams per class: one wave each of the two small classes and two of the large one in
+    # flight, four streams for the GPU's four hardware queues -- more streams than queues put
+    # small waves behind large ones on a shared queue (measured at 20k shots/s: 64-class p99
+    # 303 ms with four streams per class, 60 ms with these)
+    STREAMS = {64: 1, 128: 1, 256: 2}
+
+    def __init__(self, budget_bytes, class_share=None, max_wave=256, streams_per_class=None, flags=0,
+                 keep_results=False, device="cuda", slot_steps=None):
         self.device = device
         self.flags = int(flags)
         self.max_wave = int(max_wave)
         self.keep = bool(keep_results)
         share = class_share or {64: 0.04, 128: 0.12, 256: 0.84}
+        if streams_per_class is None:
+            streams_per_class = {side: self.STREAMS.get(side, 1) for side in share}
+        elif not isinstance(streams_per_class, dict):
+            streams_per_class = {side: int(streams_per_class) for side in share}
         self.classes = {}
+        slot_steps = slot_steps or {}
         for side, f in share.items():
-            n = int(budget_bytes * f) // _Class.slot_bytes(side)
+            n = int(budget_bytes * f) // _Class.slot_bytes(side, slot_steps.get(side))
             if n > 0:
-                self.classes[side] = _Class(side, n, streams_per_class, device)
+                self.classes[side] = _Class(side, n, streams_per_class[side], device, slot_steps.get(side))
+        self.rerun_stream = torch.cuda.Stream(device=device)
         self.waiting = {side: collections.deque() for side in self.classes}
         self.inflight = []
         self.shots = []
@@ -186,6 +201,12 @@ class Server:
             rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, flags_for(c.side, self.flags),
                                 c.batches, c.steps,
                                 w.binfo, c.ws, c.ws.numel() * 8, st)
+            # the infos come back on the wave's own stream, into pinned buffers the host reads
+            # once the event has fired: retiring a wave never waits on the device
+            w.sinfo_h = torch.empty(w.sinfo.numel(), dtype=torch.int32, pin_memory=True)
+            w.binfo_h = torch.empty(w.binfo.numel(), dtype=torch.int32, pin_memory=True)
+            w.sinfo_h.copy_(w.sinfo, non_blocking=True)
+            w.binfo_h.copy_(w.binfo, non_blocking=True)
             w.event = torch.cuda.Event()
             w.event.record(st)
         w.cls, w.ids, w.slots, w.launched = c, ids, slots, time.perf_counter()
@@ -201,17 +222,20 @@ class Server:
                 still.append(w)
                 continue
             now = time.perf_counter()
-            si = w.sinfo.cpu().numpy().view(np.uint32).reshape(-1, SOLVE_INFO_WORDS)
-            bi = w.binfo.cpu().numpy().view(np.uint32).reshape(-1, BATCH_INFO_WORDS)
+            if w.cls is None:                          # a shot re-run alone with exact buffers
+                self._retire_rerun(w, now)
+                continue
+            si = w.sinfo_h.numpy().view(np.uint32).reshape(-1, SOLVE_INFO_WORDS)
+            bi = w.binfo_h.numpy().view(np.uint32).reshape(-1, BATCH_INFO_WORDS)
             for k, i in enumerate(w.ids):
                 sh = self.shots[i]
                 sh["t_launch"] = w.launched
                 if np.int32(bi[k, 0]) == RR_E_CAPACITY and np.int32(si[k, 0]) == RR_OK:
-                    self._rerun_alone(i, int(si[k, 3]))    # more steps than the slot holds
-                else:
-                    sh["sinfo"], sh["binfo"] = si[k].copy(), bi[k].copy()
-                    if self.keep:
-                        sh["out"] = self._copy_out(w.cls, w.slots[k], sh, si[k], bi[k])
+                    still.append(self._launch_rerun(i, int(si[k, 3])))   # more steps than the slot holds
+                    continue
+                sh["sinfo"], sh["binfo"] = si[k].copy(), bi[k].copy()
+                if self.keep:
+                    sh["out"] = self._copy_out(w.cls, w.slots[k], sh, si[k], bi[k])
                 sh["t_done"] = time.perf_counter() if self.keep else now
             for s in w.slots:
                 w.cls.free.append(s)
@@ -238,17 +262,32 @@ class Server:
             bat["steps"] = sp.view(np.uint32).copy()
         return sol, bat
 
-    def _rerun_alone(self, i, n_steps):
+    def _launch_rerun(self, i, n_steps):
+        """Re-run shot i alone with buffers sized to its exact step count, on the re-run stream,
+        as a wave of its own (retired by its event like the others; nothing waits for it)."""
         self.overflow += 1
         sh = self.shots[i]
-        sb = SolveBuffers(sh["shape"], device=self.device).load(sh["grid"]).run()
-        bb = BatchBuffers(sb, step_cap=max(n_steps, 1), device=self.device).run(self.flags)
-        torch.cuda.synchronize()
-        sol, bat = sb.host(), bb.host()
+        w = _Wave()
+        w.cls, w.ids, w.slots, w.launched = None, [i], [], time.perf_counter()
+        st = self.rerun_stream
+        with torch.cuda.stream(st):
+            w.sb = SolveBuffers(sh["shape"], device=self.device)
+            w.sb.occ.copy_(torch.from_numpy(sh["grid"].view(np.int64)).to(self.device, non_blocking=False))
+            w.sb.run(st)
+            w.bb = BatchBuffers(w.sb, step_cap=max(n_steps, 1), device=self.device).run(self.flags, st)
+            w.event = torch.cuda.Event()
+            w.event.record(st)
+        return w
+
+    def _retire_rerun(self, w, now):
+        i = w.ids[0]
+        sh = self.shots[i]
+        sol, bat = w.sb.host(), w.bb.host()
         sh["sinfo"] = np.array([sol["status"], sol["n_moves"], sol["n_groups"], sol["n_steps"], 0, 0], np.uint32)
         sh["binfo"] = np.array([bat["status"], bat["n_batches"], bat["n_steps"], 0, 0], np.uint32)
         if self.keep:
             sh["out"] = (sol, bat)
+        sh["t_done"] = time.perf_counter() if self.keep else now
 
     def drain(self, timeout_s=120.0):
         t0 = time.perf_counter()

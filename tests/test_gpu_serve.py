@@ -93,3 +93,23 @@ def test_served_admission_under_a_tiny_budget():
     assert srv.waves >= 8
     for i in range(len(shots)):
         same(srv.result(i), alone(shapes[i], grids[i]), f"tiny {i}")
+
+
+def test_served_overflow_rerun_is_asynchronous_and_exact():
+    """Slots too small for every shot's steps: each shot comes back RR_E_CAPACITY from its wave
+    and is re-run alone on the server's own stream, retired by its event while other waves keep
+    going; every result equals its single-instance launch."""
+    from paper_2504_06182_amd.serve import Server
+    shots = ri.config_shots("batch64", n=12)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    say("case served overflow")
+    srv = Server(budget_bytes=1 << 30, class_share={64: 1.0}, max_wave=4, keep_results=True,
+                 slot_steps={64: 4096}, streams_per_class={64: 2})
+    for k in range(len(shots)):
+        srv.submit(shapes[k], grids[k])
+        srv.pump()
+    srv.drain()
+    assert srv.overflow == len(shots)
+    for i in range(len(shots)):
+        same(srv.result(i), alone(shapes[i], grids[i]), f"overflow {i}")
