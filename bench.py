@@ -354,7 +354,7 @@ def variants_form(args, dev):
     import rr_inputs as ri
     import paper_2504_06182_amd as rr
     from paper_2504_06182_amd.pipeline import ManyBuffers
-    from paper_2504_06182_amd.tune import flags_for
+    from paper_2504_06182_amd.tune import flags_for, solve_flags_for
     shots = ri.config_shots(WORKLOAD)
     shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
     grids = [ri.shot_grid(d) for d in shots]
@@ -363,7 +363,7 @@ def variants_form(args, dev):
     ws_one = rr.rr_batch_workspace_bytes(shapes[0], 2 * 44 * 44, STEP_BOUND_PER_SHOT)
     out = {}
     for name, algo in (("redrec_parallel", 0), ("redrec_serial", 1), ("bird", 2)):
-        mb = ManyBuffers(shapes, device=dev, solve_flags=algo).load(grids)
+        mb = ManyBuffers(shapes, device=dev, solve_flags=solve_flags_for(64, algo)).load(grids)
         n = mb.n
         mb.alloc_pools(n * STEP_BOUND_PER_SHOT, n * (STEP_BOUND_PER_SHOT + 1), n * ((ws_one + 255) // 256 * 256))
         ts, tb = [], []
@@ -534,7 +534,7 @@ def main():
         rrbuild.build()
     import paper_2504_06182_amd as rr
     from paper_2504_06182_amd.pipeline import BatchBuffers, ManyBuffers, SolveBuffers
-    from paper_2504_06182_amd.tune import flags_for
+    from paper_2504_06182_amd.tune import flags_for, solve_flags_for
     rr.lib()
     torch.cuda.set_device(0)
     dev = "cuda:0"
@@ -543,7 +543,7 @@ def main():
     n = len(shots)
     shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
     grids = [ri.shot_grid(d) for d in shots]
-    mb = ManyBuffers(shapes, device=dev).load(grids)
+    mb = ManyBuffers(shapes, device=dev, solve_flags=solve_flags_for(64)).load(grids)
     ws_one = rr.rr_batch_workspace_bytes(shapes[0], 2 * 44 * 44, STEP_BOUND_PER_SHOT)
     mb.alloc_pools(n * STEP_BOUND_PER_SHOT, n * (STEP_BOUND_PER_SHOT + 1), n * ((ws_one + 255) // 256 * 256))
     stream = torch.cuda.current_stream()
@@ -671,7 +671,8 @@ def main():
         "config": {"workload": "8192 shots, 64x64 trap grid, i.i.d. Bernoulli(0.55) loading, centred 44x44 "
                                "target; solve + batching (line-or-column constraint) per shot",
                    "shots": n, "grid": [64, 64], "target": [44, 44], "p": 0.55, "flags": bflags,
-                   "schedule": {"graph_lds_kib": (bflags >> 24) & 0xFF, "loop_lds_kib": (bflags >> 8) & 0xFF}},
+                   "schedule": {"solve_waves_per_instance": (mb.solve_flags >> 8) & 0xF or 4,
+                                "graph_lds_kib": (bflags >> 24) & 0xFF, "loop_lds_kib": (bflags >> 8) & 0xFF}},
         "kernels_ms": {"solve_many": round(k_solve, 3), "plan_many": round(k_plan, 3), "batch_many": round(k_batch, 3),
                        "batch_graph": round(k_graph, 3), "batch_loop": round(k_loop, 3),
                        "batch_generic": round(k_generic, 3)},

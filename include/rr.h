@@ -96,6 +96,11 @@ typedef struct {
  * y + |x - j| above the target or y - |x - j| below it; among tokens of one virtual row the
  * nearest column comes first, then the left one.  One group per such column. */
 #define RR_BIRD            2u
+/* Wavefronts per instance of the solve kernels (flags bits 8..11): 1, 2 or 4 (0 = the default,
+ * 4).  A launch needs at least one thread per grid side: 64 * waves >= the largest side of the
+ * call's grids, else the call returns RR_E_INVAL.  A schedule knob: results do not depend on
+ * it. */
+#define RR_SOLVE_WAVES(n)  ((uint32_t)(n) << 8)
 
 /* Largest grid side the device kernels take. */
 #define RR_MAX_SIDE 256u
@@ -115,7 +120,8 @@ size_t rr_solve_workspace_bytes(rr_shape shape);
  *                    surplus with moves, one per receiver column in the order it was saturated.
  *   final_occ  [out] bit rows of the grid after all moves (H*ws words).
  *   info       [out] one rr_solve_info.
- *   flags      [in]  RR_REDREC_PARALLEL, RR_REDREC_SERIAL or RR_BIRD (any other value: RR_E_INVAL).
+ *   flags      [in]  bits 0..7: RR_REDREC_PARALLEL, RR_REDREC_SERIAL or RR_BIRD; bits 8..11:
+ *                    RR_SOLVE_WAVES(1, 2 or 4) or 0; other bits 0 (else RR_E_INVAL).
  * An instance is solved iff F = N - D - (x1-x0)*(y1-y0) >= 0, decided before any move: N is
  * the number of tokens and D the number of target-row tokens beyond the target width,
  * counted only when the target leaves side columns (the row pre-pass parks those tokens in

@@ -21,15 +21,16 @@
 
 namespace rr {
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / kWave;
+constexpr int kThreads = 256;              // default threads per instance (4 waves)
 
 enum { M_STEPS = 0, M_NEV = 1, M_ERR = 2, M_CNT = 3 };
 
 constexpr uint32_t kOrderSerial = 1u;   // RR_REDREC_SERIAL
 constexpr uint32_t kBird = 2u;          // RR_BIRD
 
-template <int S>
+// NW waves per instance; the per-wave scratch P, Q has at least three rows (the pair loop, the
+// serial donor solves and bird use rows 0..2 from one wave)
+template <int S, int NW>
 struct SolveLds {
     static constexpr int WS = S / 64;
     uint64_t rows[S * WS];   // bit rows, stride ws
@@ -47,12 +48,12 @@ struct SolveLds {
     // bird: histograms of reservoir tokens by virtual distance from the band (above: u = v - y1,
     // below: u = y0 - 1 - v) and their exclusive prefix counts and sums of virtual rows
     int hT[2 * S + 2], hB[2 * S + 2], cT[2 * S + 3], cB[2 * S + 3], sT[2 * S + 3], sB[2 * S + 3];
-    int P[kWaves][S + 1];
-    int Q[kWaves][S + 2];
+    int P[NW < 3 ? 3 : NW][S + 1];
+    int Q[NW < 3 ? 3 : NW][S + 2];
     uint64_t rkey[S];
     int16_t ry[S], rorg[S], byRank[S];
-    int scanA[kWaves];
-    int scanB[kWaves];
+    int scanA[NW];
+    int scanB[NW];
     int misc[8];
 };
 
@@ -71,6 +72,7 @@ struct SolveArgs {
 // ------------------------------------------------------------------------------------------
 // workgroup helpers
 
+template <int NW>
 __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
 {
     const int lane = lane_id(), wid = threadIdx.x >> 6;
@@ -79,7 +81,7 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
     __syncthreads();
     int off = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
+    for (int w = 0; w < NW; ++w) {
         int t = tmp[w];
         off += (w < wid) ? t : 0;
         tot += t;
@@ -89,10 +91,11 @@ __device__ __forceinline__ int block_excl_scan(int v, int *tmp, int *total)
     return off + inc - v;
 }
 
+template <int NW>
 __device__ __forceinline__ int block_sum(int v, int *tmp)
 {
     int tot;
-    block_excl_scan(v, tmp, &tot);
+    block_excl_scan<NW>(v, tmp, &tot);
     return tot;
 }
 
@@ -225,8 +228,8 @@ __device__ __forceinline__ int remaining_rows_wave(const int *F, int a, int bc, 
 // ------------------------------------------------------------------------------------------
 // donor/receiver loop (Alg. 1 main loop, pairing rule of §III.C), run by wave 0
 
-template <int S>
-__device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
+template <int S, int NW>
+__device__ void pair_loop(SolveLds<S, NW> &L, int W, int hs, int y0, int y1, int sh)
 {
     const int lane = lane_id();
     constexpr int CW = S / 64;
@@ -382,8 +385,8 @@ __device__ void pair_loop(SolveLds<S> &L, int W, int hs, int y0, int y1, int sh)
 // Column x once settled: its band full (central) or its parked band tokens (side), plus, for a
 // donor, the pool left in its reservoir -- indices [0, bcnt) and [ubeg, a) of its sorted
 // eligible rows.
-template <int S>
-__device__ __forceinline__ void settle_column(SolveLds<S> &L, int x, int hs, int y0, int y1, bool central, bool donor)
+template <int S, int NW>
+__device__ __forceinline__ void settle_column(SolveLds<S, NW> &L, int x, int hs, int y0, int y1, bool central, bool donor)
 {
     int keepLow = L.bcnt[x], dropLow = L.ubeg[x];
     for (int sl = 0; sl < hs; ++sl) {
@@ -437,9 +440,10 @@ __device__ __forceinline__ int diag_rank(const uint64_t *cols, int hs, int W, in
     return q;
 }
 
-template <int S>
-__device__ void bird_columns(SolveLds<S> &L, const SolveArgs &A, int &off, int &g)
+template <int S, int T>
+__device__ void bird_columns(SolveLds<S, T / kWave> &L, const SolveArgs &A, int &off, int &g)
 {
+    constexpr int kThreads = T, kWaves = T / kWave;
     const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
     const int W = A.W, H = A.H, x0 = A.x0, y0 = A.y0, x1 = A.x1, y1 = A.y1, sh = y1 - y0;
     const int hs = (H + 63) >> 6;
@@ -575,8 +579,8 @@ __device__ void bird_columns(SolveLds<S> &L, const SolveArgs &A, int &off, int &
             dn = moving && !isUp;
         }
         int nUp, nDn;
-        const int upEx = block_excl_scan(up, L.scanA, &nUp);
-        const int dnEx = block_excl_scan(dn, L.scanB, &nDn);
+        const int upEx = block_excl_scan<kWaves>(up, L.scanA, &nUp);
+        const int dnEx = block_excl_scan<kWaves>(dn, L.scanB, &nDn);
         if (up) put_move(A, (uint32_t)(off + nUp - (upEx + 1)), x, y, j, t);
         if (dn) put_move(A, (uint32_t)(off + nUp + dnEx), x, y, j, t);
         int st = (up || dn) ? ((x > j ? x - j : j - x) + (t > y ? t - y : y - t)) : 0;
@@ -596,9 +600,11 @@ __device__ void bird_columns(SolveLds<S> &L, const SolveArgs &A, int &off, int &
 
 // ------------------------------------------------------------------------------------------
 
-template <int S>
-__device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
+template <int S, int T>
+__device__ void solve_one(SolveLds<S, T / kWave> &L, const SolveArgs &A)
 {
+    constexpr int kThreads = T, kWaves = T / kWave;
+    static_assert(T >= S && T % kWave == 0, "one thread per grid side at least");
     const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
     const int W = A.W, H = A.H, x0 = A.x0, y0 = A.y0, x1 = A.x1, y1 = A.y1;
     const int sw = x1 - x0, sh = y1 - y0;
@@ -625,8 +631,8 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
         myN = a;
         if (side && tid >= y0 && tid < y1) myD = a > sw ? a - sw : 0;
     }
-    const int N = block_sum(myN, L.scanA);
-    const int D = block_sum(myD, L.scanB);
+    const int N = block_sum<kWaves>(myN, L.scanA);
+    const int D = block_sum<kWaves>(myD, L.scanB);
     if ((long)N - D - (long)sw * sh < 0) {
         for (int i = tid; i < H * ws; i += kThreads) A.fin[i] = L.rows[i];
         if (tid == 0) {
@@ -659,8 +665,8 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
         }
         __syncthreads();
         const int cnt = tid < sh ? L.rowCnt[y0 + tid] : 0;
-        const int off = block_excl_scan(cnt, L.scanA, &nH);
-        const int gi = block_excl_scan(cnt > 0 ? 1 : 0, L.scanB, &gH);
+        const int off = block_excl_scan<kWaves>(cnt, L.scanA, &nH);
+        const int gi = block_excl_scan<kWaves>(cnt > 0 ? 1 : 0, L.scanB, &gH);
         if (tid < sh) {
             L.rowOff[y0 + tid] = off;
             if (cnt > 0 && gi <= (int)A.group_cap) A.goff[gi] = (uint32_t)off;
@@ -746,8 +752,8 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     int nA, gA;
     {
         const int cnt = tid < W ? L.colCnt[tid] : 0;
-        const int off = block_excl_scan(cnt, L.scanA, &nA);
-        const int gi = block_excl_scan(cnt > 0 ? 1 : 0, L.scanB, &gA);
+        const int off = block_excl_scan<kWaves>(cnt, L.scanA, &nA);
+        const int gi = block_excl_scan<kWaves>(cnt > 0 ? 1 : 0, L.scanB, &gA);
         if (tid < W) {
             L.colOff[tid] = nH + off;
             if (cnt > 0 && gH + gi <= (int)A.group_cap) A.goff[gH + gi] = (uint32_t)(nH + off);
@@ -766,12 +772,12 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     if (birdAlg) {
         // ---- bird: the grid after the non-negative columns (band full, their excess where it
         //      stood), then the negative columns leftmost first ----------------------------------
-        if (tid < W && tid >= x0 && tid < x1 && L.sig[tid] >= 0) settle_column<S>(L, tid, hs, y0, y1, true, true);
+        if (tid < W && tid >= x0 && tid < x1 && L.sig[tid] >= 0) settle_column<S, kWaves>(L, tid, hs, y0, y1, true, true);
         __syncthreads();
-        bird_columns<S>(L, A, off, g);
+        bird_columns<S, T>(L, A, off, g);
     } else {
     // ---- donor/receiver pairs ---------------------------------------------------------------
-    if (wid == 0) pair_loop<S>(L, W, hs, y0, y1, sh);
+    if (wid == 0) pair_loop<S, kWaves>(L, W, hs, y0, y1, sh);
     __syncthreads();
     const int nev = L.misc[M_NEV];
 
@@ -824,8 +830,8 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
             dn = moving && t < y;
         }
         int nUp, nDn;
-        const int upEx = block_excl_scan(up, L.scanA, &nUp);
-        const int dnEx = block_excl_scan(dn, L.scanB, &nDn);
+        const int upEx = block_excl_scan<kWaves>(up, L.scanA, &nUp);
+        const int dnEx = block_excl_scan<kWaves>(dn, L.scanB, &nDn);
         if (up) put_move(A, (uint32_t)(off + nUp - (upEx + 1)), o, y, j, t);
         if (dn) put_move(A, (uint32_t)(off + nUp + dnEx), o, y, j, t);
         int st = (up || dn) ? ((o > j ? o - j : j - o) + (t > y ? t - y : y - t)) : 0;
@@ -893,8 +899,8 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
         const int x = x0 + tid;
         const bool last = x < x1 && !L.dsol[x];
         const int cnt = last ? L.colCnt[x] : 0;
-        const int zoff = block_excl_scan(cnt, L.scanA, &nZ);
-        const int gi = block_excl_scan(cnt > 0 ? 1 : 0, L.scanB, &gZ);
+        const int zoff = block_excl_scan<kWaves>(cnt, L.scanA, &nZ);
+        const int gi = block_excl_scan<kWaves>(cnt > 0 ? 1 : 0, L.scanB, &gZ);
         if (cnt > 0) {
             L.colOff[x] = off + zoff;
             if (g + gi <= (int)A.group_cap) A.goff[g + gi] = (uint32_t)(off + zoff);
@@ -923,7 +929,7 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     // ---- final grid: band full in central columns, parked tokens, remaining pools -----------
     if (tid < W) {
         const bool central = (tid >= x0 && tid < x1);
-        settle_column<S>(L, tid, hs, y0, y1, central, !central || L.sig[tid] >= 0);
+        settle_column<S, kWaves>(L, tid, hs, y0, y1, central, !central || L.sig[tid] >= 0);
     }
     __syncthreads();
     }
@@ -952,19 +958,19 @@ __device__ void solve_one(SolveLds<S> &L, const SolveArgs &A)
     }
 }
 
-template <int S>
-__global__ __launch_bounds__(kThreads) void k_solve_one(SolveArgs A)
+template <int S, int T>
+__global__ __launch_bounds__(T) void k_solve_one(SolveArgs A)
 {
-    __shared__ SolveLds<S> L;
-    solve_one<S>(L, A);
+    __shared__ SolveLds<S, T / kWave> L;
+    solve_one<S, T>(L, A);
 }
 
-template <int S>
-__global__ __launch_bounds__(kThreads) void k_solve_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
-                                                         const uint64_t *occ, rr_move *mv, uint32_t *ga,
-                                                         uint64_t *fa, rr_solve_info *infos, uint32_t flags)
+template <int S, int T>
+__global__ __launch_bounds__(T) void k_solve_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
+                                                  const uint64_t *occ, rr_move *mv, uint32_t *ga,
+                                                  uint64_t *fa, rr_solve_info *infos, uint32_t flags)
 {
-    __shared__ SolveLds<S> L;
+    __shared__ SolveLds<S, T / kWave> L;
     const rr_desc d = desc[blockIdx.x];
     const rr_shape s = d.shape;
     const bool ok = s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= S && s.h <= S &&
@@ -986,7 +992,7 @@ __global__ __launch_bounds__(kThreads) void k_solve_many(const rr_desc *__restri
     A.group_cap = d.group_cap;
     A.fin = fa + d.occ_off;
     A.info = infos + blockIdx.x;
-    solve_one<S>(L, A);
+    solve_one<S, T>(L, A);
 }
 
 }  // namespace rr
@@ -1000,7 +1006,31 @@ static bool shape_valid(const rr_shape &s)
 
 extern "C" size_t rr_solve_workspace_bytes(rr_shape) { return 0; }
 
-static bool flags_valid(uint32_t flags) { return flags <= RR_BIRD; }
+// flags: bits 0..7 the algorithm, bits 8..11 wavefronts per instance (0: the default, 4)
+static bool flags_valid(uint32_t flags)
+{
+    const uint32_t algo = flags & 0xFFu, waves = (flags >> 8) & 0xFu;
+    return algo <= RR_BIRD && (flags >> 12) == 0u && (waves == 0u || waves == 1u || waves == 2u || waves == 4u);
+}
+
+static uint32_t threads_of(uint32_t flags)
+{
+    const uint32_t waves = (flags >> 8) & 0xFu;
+    return 64u * (waves ? waves : (uint32_t)(kThreads / kWave));
+}
+
+// one launch of the solve kernel for size class S (largest grid side) at T threads per instance
+#define RR_SOLVE_DISPATCH(LAUNCH, SIDE, T, OK)                                                              \
+    do {                                                                                                    \
+        OK = true;                                                                                          \
+        if (SIDE <= 64 && T == 64) LAUNCH(64, 64);                                                          \
+        else if (SIDE <= 64 && T == 128) LAUNCH(64, 128);                                                   \
+        else if (SIDE <= 64 && T == 256) LAUNCH(64, 256);                                                   \
+        else if (SIDE > 64 && SIDE <= 128 && T == 128) LAUNCH(128, 128);                                    \
+        else if (SIDE > 64 && SIDE <= 128 && T == 256) LAUNCH(128, 256);                                    \
+        else if (SIDE > 128 && T == 256) LAUNCH(256, 256);                                                  \
+        else OK = false;                                                                                    \
+    } while (0)
 
 extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *moves, uint32_t move_cap,
                               uint32_t *group_off, uint32_t group_cap, uint64_t *final_occ,
@@ -1018,10 +1048,13 @@ extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *move
     A.occ = occ; A.moves = moves; A.move_cap = move_cap; A.goff = group_off; A.group_cap = group_cap;
     A.fin = final_occ; A.info = info;
     hipStream_t st = (hipStream_t)stream;
-    const int side = shape.w > shape.h ? shape.w : shape.h;
-    if (side <= 64) hipLaunchKernelGGL(k_solve_one<64>, dim3(1), dim3(kThreads), 0, st, A);
-    else if (side <= 128) hipLaunchKernelGGL(k_solve_one<128>, dim3(1), dim3(kThreads), 0, st, A);
-    else hipLaunchKernelGGL(k_solve_one<256>, dim3(1), dim3(kThreads), 0, st, A);
+    const uint32_t side = shape.w > shape.h ? shape.w : shape.h;
+    const uint32_t T = threads_of(flags);
+    bool ok;
+#define RR_LAUNCH_ONE(SS, TT) hipLaunchKernelGGL((k_solve_one<SS, TT>), dim3(1), dim3(TT), 0, st, A)
+    RR_SOLVE_DISPATCH(RR_LAUNCH_ONE, side, T, ok);
+#undef RR_LAUNCH_ONE
+    if (!ok) return RR_E_INVAL;                  // fewer threads per instance than the grid side
     return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
 }
 
@@ -1039,15 +1072,14 @@ extern "C" rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max
     if (((uintptr_t)move_arena & 7u) != 0) return RR_E_INVAL;
     hipStream_t st = (hipStream_t)stream;
     const uint32_t side = max_w > max_h ? max_w : max_h;
-    if (side <= 64)
-        hipLaunchKernelGGL(k_solve_many<64>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
-                           occ_arena, move_arena, group_arena, final_arena, infos, flags);
-    else if (side <= 128)
-        hipLaunchKernelGGL(k_solve_many<128>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
-                           occ_arena, move_arena, group_arena, final_arena, infos, flags);
-    else
-        hipLaunchKernelGGL(k_solve_many<256>, dim3(n), dim3(kThreads), 0, st, desc, (int)max_w, (int)max_h,
-                           occ_arena, move_arena, group_arena, final_arena, infos, flags);
+    const uint32_t T = threads_of(flags);
+    bool ok;
+#define RR_LAUNCH_MANY(SS, TT)                                                                              \
+    hipLaunchKernelGGL((k_solve_many<SS, TT>), dim3(n), dim3(TT), 0, st, desc, (int)max_w, (int)max_h,       \
+                       occ_arena, move_arena, group_arena, final_arena, infos, flags)
+    RR_SOLVE_DISPATCH(RR_LAUNCH_MANY, side, T, ok);
+#undef RR_LAUNCH_MANY
+    if (!ok) return RR_E_INVAL;                  // fewer threads per instance than the grid side
     return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
 }
 

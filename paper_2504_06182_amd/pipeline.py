@@ -10,7 +10,7 @@ import torch
 
 from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_moves_many_staged, rr_batch_workspace_bytes,
                rr_plan_many, rr_solve, rr_solve_chains, rr_solve_chains_workspace_bytes, rr_solve_many)
-from .tune import flags_for
+from .tune import flags_for, solve_flags_for
 
 SOLVE_INFO_WORDS = 6   # rr_solve_info: int32 status + 5 x uint32
 BATCH_INFO_WORDS = 5   # rr_batch_info: int32 status + 4 x uint32
@@ -312,7 +312,7 @@ class ClassedBuffers:
     one stream per class), with no host synchronisation, so the whole pass can be captured in a
     graph and replayed."""
 
-    def __init__(self, shapes, step_bound, device="cuda"):
+    def __init__(self, shapes, step_bound, device="cuda", algo=0):
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.n = len(self.shapes)
         self.device = device
@@ -324,7 +324,7 @@ class ClassedBuffers:
             if c not in by:
                 continue
             idx = np.array(by[c], np.int64)
-            mb = ManyBuffers([self.shapes[i] for i in idx], device=device)
+            mb = ManyBuffers([self.shapes[i] for i in idx], device=device, solve_flags=solve_flags_for(c, algo))
             self.parts.append((c, idx, mb))
         self.step_bound = step_bound
         for _, idx, mb in self.parts:

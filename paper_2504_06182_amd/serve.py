@@ -30,7 +30,7 @@ import numpy as np
 import torch
 
 from . import RR_E_CAPACITY, RR_OK, rr_batch_moves_many, rr_batch_workspace_bytes, rr_solve_many
-from .tune import flags_for
+from .tune import flags_for, solve_flags_for
 from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuffers, SolveBuffers,
                        solve_caps, words_per_row)
 
@@ -197,7 +197,8 @@ class Server:
             c.occ.view(c.n, c.occ_words).index_copy_(0, idx, rows)
             w.sinfo = torch.empty(n * SOLVE_INFO_WORDS, dtype=torch.int32, device=self.device)
             w.binfo = torch.empty(n * BATCH_INFO_WORDS, dtype=torch.int32, device=self.device)
-            rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo, 0, None, 0, st)
+            rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo,
+                          solve_flags_for(c.side), None, 0, st)
             rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, flags_for(c.side, self.flags),
                                 c.batches, c.steps,
                                 w.binfo, c.ws, c.ws.numel() * 8, st)

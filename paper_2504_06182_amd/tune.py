@@ -1,6 +1,8 @@
-"""Launch-schedule autotuner for the batching kernels.
+"""Launch-schedule autotuner for the solve and batching kernels.
 
-A batching call carries two schedule knobs in its flags word (include/rr.h):
+A solve call carries one schedule knob in its flags word (include/rr.h): bits 8..11, the
+wavefronts per instance (1, 2 or 4; at least one thread per grid side), i.e. how many waves
+work one shot and how many shots a CU holds.  A batching call carries two:
   * bits 24..31 -- the graph kernel's LDS tile budget in KiB: how much of a grid's per-trap
     lists one workgroup holds at a time, hence workgroups per CU and, for large grids, the
     number of row ranges of the tiled build;
@@ -26,6 +28,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "schedules.json")
 
+SOLVE_WAVES = {64: (1, 2, 4), 128: (2, 4), 192: (4,), 256: (4,)}   # wavefronts per instance per class
+DEFAULT_SOLVE_WAVES = 4
 GRAPH_KIB = (24, 32, 48, 64, 96, 128, 150)
 LOOP_KIB = (1, 4, 8, 16, 32, 64)
 DEFAULT_GRAPH_KIB, DEFAULT_LOOP_KIB = 64, 1    # the library's own many-instance budgets
@@ -38,6 +42,21 @@ def schedule_bits(graph_kib: int, loop_kib: int) -> int:
     if not (1 <= graph_kib <= 255 and 1 <= loop_kib <= 255):
         raise ValueError("LDS budgets are 1..255 KiB")
     return (int(graph_kib) << 24) | (int(loop_kib) << 8)
+
+
+def solve_flags_for(size_class: int, algo: int = 0, table: dict | None = None) -> int:
+    """Solve flags for a class: the algorithm ``algo`` (bits 0..7) with the class's tuned
+    wavefronts per instance (bits 8..11) -- unless ``algo`` sets them already."""
+    algo = int(algo)
+    if algo & (0xF << 8):
+        return algo
+    if table is None:
+        if "t" not in _cache:
+            _cache["t"] = load_table()
+        table = _cache["t"]
+    e = table["classes"].get(str(int(size_class)))
+    w = int(e.get("solve_waves", 0)) if e else 0
+    return algo | (w << 8)
 
 
 def load_table(path: str = TABLE) -> dict:
@@ -126,6 +145,43 @@ def _pick(times: dict, default: int) -> int:
     return best
 
 
+def _solve_run(mb, flags, reps):
+    """Solve every instance of ``mb`` ``reps`` times under solve flags ``flags``; the best
+    kernel time (ms) and the outputs of the last run (arenas cleared before each run)."""
+    import torch
+
+    best = float("inf")
+    mb.solve_flags = int(flags)
+    for _ in range(reps):
+        for t in (mb.moves, mb.groups, mb.final, mb.sinfo):
+            t.zero_()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        e[0].record()
+        mb.solve()
+        e[1].record()
+        torch.cuda.synchronize()
+        best = min(best, e[0].elapsed_time(e[1]))
+    return best, (mb.sinfo.clone(), mb.moves.clone(), mb.groups.clone(), mb.final.clone())
+
+
+def tune_solve(mb, side: int, reps: int = 3) -> dict:
+    """Pick the wavefronts per instance of the solve for one size class (``mb`` loaded, the
+    launch size of the workload); raises when a candidate's outputs differ from the default's."""
+    import torch
+
+    _, ref = _solve_run(mb, DEFAULT_SOLVE_WAVES << 8, 1)
+    times = {}
+    for w in SOLVE_WAVES[side]:
+        t, out = _solve_run(mb, w << 8, reps)
+        if not all(torch.equal(a, b) for a, b in zip(out, ref)):
+            raise RuntimeError(f"{w} wavefronts per instance changed the solve outputs")
+        times[w] = t
+    mb.solve_flags = 0
+    best = _pick(times, DEFAULT_SOLVE_WAVES)
+    return {"solve_waves": best, "solve_ms": round(times[best], 3),
+            "solve_ms_by_waves": {str(k): round(v, 3) for k, v in times.items()}}
+
+
 def tune_class(mb, constraint: int = 0, graph_kib=GRAPH_KIB, loop_kib=LOOP_KIB, reps: int = 3) -> dict:
     """Pick the schedule of one size class.  ``mb``: a solved ManyBuffers of that class whose
     batching arenas are planned (plan_batches), holding as many shots as the launches to be
@@ -163,11 +219,13 @@ def tune(shots_by_class: dict, constraint: int = 0, reps: int = 3, **kw) -> dict
 
     out = {"device": torch.cuda.get_device_name(), "constraint": int(constraint) & 0xFF, "classes": {}}
     for c, (shapes, grids) in sorted(shots_by_class.items()):
-        mb = ManyBuffers(shapes).load(grids).solve()
+        mb = ManyBuffers(shapes).load(grids)
+        sv = tune_solve(mb, int(c), reps)
+        mb.solve()
         torch.cuda.synchronize()
         infos = mb.solve_infos()
         mb.plan_batches([max(int(i[3]), 1) for i in infos])
-        out["classes"][str(int(c))] = tune_class(mb, constraint, reps=reps, **kw)
+        out["classes"][str(int(c))] = {**tune_class(mb, constraint, reps=reps, **kw), **sv}
         del mb
         torch.cuda.empty_cache()
     return out

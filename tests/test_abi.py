@@ -87,3 +87,14 @@ def test_noalloc_refuses_oversized_workspace_before_launch():
     assert rc == rr.RR_E_NOMEM
     rc = rr.rr_batch_moves_noalloc((300, 300, 1, 1, 2, 2), 8, 8, 8, 2, 0, 8, 8, 8, 8, 8, stream=0, check=False)
     assert rc == rr.RR_E_UNSUPPORTED
+
+
+def test_solve_waves_per_instance_checked_before_launch():
+    """Wavefronts per instance (flags bits 8..11): 1, 2 or 4, at least one thread per grid side;
+    anything else is refused before any launch."""
+    for shape, waves in (((100, 100, 10, 10, 90, 90), 1), ((200, 200, 10, 10, 190, 190), 2),
+                         ((32, 32, 8, 8, 24, 24), 3), ((32, 32, 8, 8, 24, 24), 8)):
+        rc = rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, waves << 8, None, 0, stream=0, check=False)
+        assert rc == rr.RR_E_INVAL, (shape, waves)
+    rc = rr.rr_solve_many(1, 8, 200, 200, 8, 8, 8, 8, 8, 2 << 8, None, 0, stream=0, check=False)
+    assert rc == rr.RR_E_INVAL

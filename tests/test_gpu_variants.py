@@ -200,3 +200,30 @@ def test_variant_many_instances_batch64_and_mixed(algo):
             if r["status"] == 0 and shapes[i][0] <= 128:
                 rb = oracle.batch(shapes[i], r["moves"], r["group_off"], r["n_steps"], indexed=True)
                 same_batch(mb.host_batch(i, binf), rb, f"{name} batch {i}")
+
+
+@pytest.mark.parametrize("algo", [0, SERIAL, BIRD], ids=["parallel", "serial", "bird"])
+def test_solve_wavefronts_per_instance_do_not_change_results(algo):
+    """Every size class solved with each wavefront count it can take (64: 1, 2, 4; 128: 2, 4;
+    256: 4) in one-instance and many-instance launches: the same bytes."""
+    from paper_2504_06182_amd.pipeline import ManyBuffers, SolveBuffers
+    shots = [d for d in ri.config_shots("mixed", n=80) if d["w"] <= 128][:36]
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    for cls, waves in ((64, (1, 2, 4)), (128, (2, 4))):
+        idx = [i for i, s in enumerate(shapes) if (s[0] <= 64) == (cls == 64)]
+        say("case waves", NAMES.get(algo, "parallel"), cls, waves, len(idx))
+        ref = None
+        for w in waves:
+            mb = ManyBuffers([shapes[i] for i in idx], solve_flags=algo | (w << 8)).load([grids[i] for i in idx])
+            mb.solve()
+            torch.cuda.synchronize()
+            inf = mb.solve_infos()
+            outs = [mb.host_solve(k, inf) for k in range(mb.n)]
+            if ref is None:
+                ref = outs
+            for k in range(mb.n):
+                same_solve(outs[k], ref[k], f"class {cls} waves {w} shot {k}")
+            sb = SolveBuffers(shapes[idx[0]], flags=algo | (w << 8)).load(grids[idx[0]]).run()
+            torch.cuda.synchronize()
+            same_solve(sb.host(), ref[0], f"one-instance class {cls} waves {w}")
