@@ -153,7 +153,9 @@ size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step
  *                    to what the loop always keeps in LDS (8 B per group and 16 B per register
  *                    position of the ready set: about 4 KiB for 64 x 64 grids); a graph budget
  *                    too small for one row of traps builds the graph in the workspace.
- *                    Bits 17..23 must be 0.
+ *                    Bits 20..23: wavefronts per instance of the graph kernel divided by 4
+ *                    (1, 2 or 4: 4, 8 or 16 wavefronts; 0 = the default, 8), another tuning
+ *                    knob.  Bits 17..19 must be 0.
  *                    At most 2^20 - 1 moves in at most 1024 groups (always true for rr_solve
  *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.
  *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).

@@ -28,19 +28,22 @@ namespace rr {
 
 // ---- graph kernels
 
-__global__ __launch_bounds__(fast::kGT) void k_graph_one(fast::Inst I, uint32_t lds_bytes, uint32_t flags)
+// NT threads per instance (graph wavefronts per instance: flags bits 20..23)
+template <int NT>
+__global__ __launch_bounds__(NT) void k_graph_one(fast::Inst I, uint32_t lds_bytes, uint32_t flags)
 {
-    __shared__ fast::GraphShared S;
-    fast::graph_build(I, S, dyn_lds, lds_bytes, (flags & kFlagGeneric) != 0);
+    __shared__ fast::GraphShared<NT / kWave> S;
+    fast::graph_build<NT>(I, S, dyn_lds, lds_bytes, (flags & kFlagGeneric) != 0);
 }
 
-__global__ __launch_bounds__(fast::kGT) void k_graph_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
+template <int NT>
+__global__ __launch_bounds__(NT) void k_graph_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                           const rr_move *mv, const uint32_t *ga,
                                                           const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
                                                           rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,
                                                           uint32_t lds_bytes, uint32_t flags)
 {
-    __shared__ fast::GraphShared S;
+    __shared__ fast::GraphShared<NT / kWave> S;
     const uint32_t i = blockIdx.x;
     const rr_desc d = desc[i];
     if (!desc_usable(d, maxw, maxh, ws_bytes)) {
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(fast::kGT) void k_graph_many(const rr_desc *__restr
         }
         return;
     }
-    fast::graph_build(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), S, dyn_lds, lds_bytes,
+    fast::graph_build<NT>(inst_of(d, i, mv, ga, sinfos, bat, stp, binfos, ws), S, dyn_lds, lds_bytes,
                       (flags & kFlagGeneric) != 0);
 }
 
@@ -198,7 +201,23 @@ static uint32_t device_lds_limit()
 struct Plan {
     int S;
     uint32_t graph_lds, loop_lds, gen_lds;
+    uint32_t graph_threads;      // threads per instance of the graph kernel
 };
+
+// batching flags: bits 17..19 zero, bits 20..23 the graph kernel's wavefronts per instance
+// divided by four (0: the default, 8 wavefronts; 1, 2 or 4: 4, 8 or 16 wavefronts)
+static bool batch_flags_valid(uint32_t flags)
+{
+    const uint32_t gw = (flags >> 20) & 0xFu;
+    return (flags & 0xFFu) <= RR_LAMBDA_NONE && ((flags >> 17) & 0x7u) == 0u &&
+           (gw == 0u || gw == 1u || gw == 2u || gw == 4u);
+}
+
+static uint32_t graph_threads_of(uint32_t flags)
+{
+    const uint32_t gw = (flags >> 20) & 0xFu;
+    return gw == 0u ? (uint32_t)fast::kGT : 256u * gw;
+}
 
 // LDS budgets.  Graph kernel: 64 KiB for grids up to 64 x 64, two workgroups per CU (a 64 x 64
 // shot of ~21k trap visits needs about 62 KiB; larger ones build in the workspace; measured:
@@ -219,7 +238,8 @@ static Plan make_plan(uint32_t flags, uint32_t max_w, uint32_t max_h, bool singl
     const uint32_t gkib = (flags >> 24) & 0xFFu;
     if (gkib) P.graph_lds = gkib * 1024u;
     else P.graph_lds = single ? 120u * 1024u : 64u * 1024u;
-    if (P.graph_lds + sizeof(fast::GraphShared) > lim) P.graph_lds = lim - (uint32_t)sizeof(fast::GraphShared);
+    if (P.graph_lds + sizeof(fast::GraphShared<16>) > lim) P.graph_lds = lim - (uint32_t)sizeof(fast::GraphShared<16>);
+    P.graph_threads = graph_threads_of(flags);
     uint32_t kib = (flags >> 8) & 0xFFu;
     if (kib == 0) kib = single ? 64u : 1u;
     P.loop_lds = kib * 1024u;
@@ -261,7 +281,7 @@ extern "C" rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const 
           shape.y1 <= shape.h))
         return RR_E_INVAL;
     if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
-    if ((flags & 0xFFu) > RR_LAMBDA_NONE || ((flags >> 17) & 0x7Fu) != 0) return RR_E_INVAL;
+    if (!batch_flags_valid(flags)) return RR_E_INVAL;
     if (!group_off || !sinfo || !batch_off || !binfo || (move_cap > 0 && !moves) || (step_cap > 0 && !steps))
         return RR_E_INVAL;
     if (((uintptr_t)moves & 7u) != 0) return RR_E_INVAL;
@@ -274,7 +294,12 @@ extern "C" rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const 
     I.ws = (uint8_t *)workspace;
     const Plan P = make_plan(flags, shape.w, shape.h, true);
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_graph_one, dim3(1), dim3(fast::kGT), P.graph_lds, st, I, P.graph_lds, flags);
+    if (P.graph_threads == 256u)
+        hipLaunchKernelGGL(k_graph_one<256>, dim3(1), dim3(256), P.graph_lds, st, I, P.graph_lds, flags);
+    else if (P.graph_threads == 1024u)
+        hipLaunchKernelGGL(k_graph_one<1024>, dim3(1), dim3(1024), P.graph_lds, st, I, P.graph_lds, flags);
+    else
+        hipLaunchKernelGGL(k_graph_one<512>, dim3(1), dim3(512), P.graph_lds, st, I, P.graph_lds, flags);
 #define RR_LOOP_ONE(SS, FF) hipLaunchKernelGGL((k_loop_one<SS, FF>), dim3(1), dim3(kWave), P.loop_lds, st, I, P.loop_lds)
 #define RR_LOOP_ONE_F(SS)                                                                                          \
     switch (flags & 0xFFu) {                                                                                       \
@@ -303,15 +328,20 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     if (n == 0) return RR_OK;
     if (!desc || !move_arena || !group_arena || !sinfos || !batch_arena || !step_arena || !binfos || !workspace)
         return RR_E_INVAL;
-    if ((flags & 0xFFu) > RR_LAMBDA_NONE || ((flags >> 17) & 0x7Fu) != 0 || max_w < 1 || max_h < 1) return RR_E_INVAL;
+    if (!batch_flags_valid(flags) || max_w < 1 || max_h < 1) return RR_E_INVAL;
     if (max_w > RR_MAX_SIDE || max_h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
     if (((uintptr_t)move_arena & 7u) != 0) return RR_E_INVAL;
     const Plan P = make_plan(flags, max_w, max_h, false);
     hipStream_t st = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
-    hipLaunchKernelGGL(k_graph_many, dim3(n), dim3(fast::kGT), P.graph_lds, st, desc, (int)max_w, (int)max_h,
-                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes,
-                       P.graph_lds, flags);
+#define RR_GRAPH_MANY(NT)                                                                                          \
+    hipLaunchKernelGGL(k_graph_many<NT>, dim3(n), dim3(NT), P.graph_lds, st, desc, (int)max_w, (int)max_h,          \
+                       move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes, \
+                       P.graph_lds, flags)
+    if (P.graph_threads == 256u) RR_GRAPH_MANY(256);
+    else if (P.graph_threads == 1024u) RR_GRAPH_MANY(1024);
+    else RR_GRAPH_MANY(512);
+#undef RR_GRAPH_MANY
     if (graph_done_event && hipEventRecord((hipEvent_t)graph_done_event, st) != hipSuccess) return RR_E_DEVICE;
 #define RR_LOOP_MANY(SS, FF)                                                                                       \
     hipLaunchKernelGGL((k_loop_many<SS, FF>), dim3(n), dim3(kWave), P.loop_lds, st, desc, (int)max_w, (int)max_h,  \

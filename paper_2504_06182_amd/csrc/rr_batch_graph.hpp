@@ -36,8 +36,7 @@ namespace fast {
 
 constexpr uint32_t kMaxK = 65535;       // move indices fit 16 bits on the fast path
 constexpr int kMaxPreds = 8;            // distinct in-group predecessors of one move
-constexpr int kGT = 512;                // threads of the graph workgroup
-constexpr int kGWaves = kGT / kWave;
+constexpr int kGT = 512;                // default threads of the graph workgroup (8 waves)
 
 // release code of a move (16 bits): kind << 14 | next - b
 constexpr uint32_t kRelNone = 0, kRelNext = 1, kRelList = 2;
@@ -140,9 +139,10 @@ __device__ __forceinline__ int path_trap(int W, int sx, int sy, int dx, int dy, 
     return (dy >= sy ? sy + v : sy - v) * W + dx;
 }
 
+template <int NW>
 struct GraphShared {
-    uint32_t part[kGWaves];
-    uint32_t red[kGWaves];
+    uint32_t part[NW];
+    uint32_t red[NW];
     uint32_t flags;
     uint32_t nr;            // row ranges of the tiled build
     uint32_t nlong;         // long horizontal legs of the current range, searched wave by wave
@@ -159,7 +159,8 @@ __device__ __forceinline__ uint32_t add_wg32(uint32_t *p, uint32_t v)
 }
 
 // workgroup sum of one value per thread (all threads get the total)
-__device__ __forceinline__ uint32_t block_sum(uint32_t v, GraphShared &S)
+template <int NT>
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, GraphShared<NT / kWave> &S)
 {
     const int lane = lane_id(), wid = threadIdx.x >> 6;
     v = (uint32_t)wave_sum((int)v);
@@ -167,17 +168,18 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, GraphShared &S)
     __syncthreads();
     uint32_t t = 0;
 #pragma unroll
-    for (int w = 0; w < kGWaves; ++w) t += S.red[w];
+    for (int w = 0; w < (NT / kWave); ++w) t += S.red[w];
     __syncthreads();
     return t;
 }
 
 // exclusive scan of a[0..n) in place, a[n] = total (a: LDS or global, visible to the workgroup)
-__device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared &S)
+template <int NT>
+__device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared<NT / kWave> &S)
 {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
     uint32_t carry = 0;
-    for (uint32_t base = 0; base <= n; base += kGT) {
+    for (uint32_t base = 0; base <= n; base += NT) {
         const uint32_t i = base + tid;
         const uint32_t v = i < n ? a[i] : 0u;
         const uint32_t inc = (uint32_t)wave_incl_scan((int)v);
@@ -185,7 +187,7 @@ __device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared 
         __syncthreads();
         uint32_t pre = 0, tot = 0;
 #pragma unroll
-        for (int w = 0; w < kGWaves; ++w) {
+        for (int w = 0; w < (NT / kWave); ++w) {
             const uint32_t pw = S.part[w];
             pre += w < wid ? pw : 0u;
             tot += pw;
@@ -245,12 +247,14 @@ __device__ __forceinline__ void set_add(uint32_t (&s)[kMaxPreds], int &n, uint32
     ++n;
 }
 
-__device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+template <int NT>
+__device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
                                           uint32_t T);
 
 // The graph of one instance from its validated moves; cell (W*H + 1 words), grp (K) and touch
 // (K + T) are the per-trap scratch arrays.
-__device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+template <int NT>
+__device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
                                            uint32_t T, uint32_t *cell, uint16_t *grp, uint16_t *touch)
 {
     const int tid = threadIdx.x;
@@ -265,31 +269,31 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
     uint32_t *gbits = (uint32_t *)(I.ws + L.gbits), *gcnt = (uint32_t *)(I.ws + L.gcnt), *hcnt = (uint32_t *)(I.ws + L.hcnt);
     const uint32_t GW = L.GW;
 
-    for (uint32_t g = tid; g < G; g += kGT)
+    for (uint32_t g = tid; g < G; g += NT)
         for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b) grp[b] = (uint16_t)g;
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         mv32[b] = (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
         sfill[b] = 0;
     }
-    for (uint32_t c = tid; c <= WH; c += kGT) cell[c] = 0;
-    for (uint32_t b = tid; b <= K; b += kGT) soff[b] = 0;
-    for (uint32_t i = tid; i < G * GW; i += kGT) gbits[i] = 0;
+    for (uint32_t c = tid; c <= WH; c += NT) cell[c] = 0;
+    for (uint32_t b = tid; b <= K; b += NT) soff[b] = 0;
+    for (uint32_t i = tid; i < G * GW; i += NT) gbits[i] = 0;
     if (tid == 0) S.flags = 0;
     __syncthreads();
 
     // ---- touch lists: count, scan, scatter (post-increment: afterwards trap c's list is
     //      [c ? cell[c-1] : 0, cell[c]))
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const int len = iabs(dx - sx) + iabs(dy - sy);
         for (int s = 0; s <= len; ++s) add_wg32(&cell[path_trap(W, sx, sy, dx, dy, s)], 1u);
     }
     __syncthreads();
-    block_scan(cell, WH, S);
-    for (uint32_t b = tid; b < K; b += kGT) {
+    block_scan<NT>(cell, WH, S);
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const int len = iabs(dx - sx) + iabs(dy - sy);
@@ -299,14 +303,14 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
         }
     }
     __syncthreads();
-    for (uint32_t c = tid; c < WH; c += kGT) {
+    for (uint32_t c = tid; c < WH; c += NT) {
         const uint32_t lo = c ? cell[c - 1] : 0u;
         sort_list(touch + lo, (int)(cell[c] - lo));
     }
     __syncthreads();
 
     // ---- previous toucher of every trap of every move
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const int len = iabs(dx - sx) + iabs(dy - sy);
@@ -346,13 +350,14 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared &S, const 
         if (tid == 0) hdr[H_STATE] = ST_GENERIC;
         return;
     }
-    graph_tail(I, S, L, K, G, T);
+    graph_tail<NT>(I, S, L, K, G, T);
 }
 
 // Second half of the graph build, from the in-group predecessor sets (pend, preds), their
 // successor counts (soff) and the group bit matrix (gbits), all in the workspace: successor
 // lists, release codes, heads, group lists and the header.
-__device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+template <int NT>
+__device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
                                           uint32_t T)
 {
     const int tid = threadIdx.x;
@@ -365,8 +370,8 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const 
     const uint32_t GW = L.GW;
 
     // ---- successor lists (CSR) and release codes
-    block_scan(soff, K, S);
-    for (uint32_t b = tid; b < K; b += kGT) {
+    block_scan<NT>(soff, K, S);
+    for (uint32_t b = tid; b < K; b += NT) {
         const uint32_t np = pend[b];
         for (uint32_t i = 0; i < np; ++i) {
             const uint32_t a = preds[(size_t)b * kMaxPreds + i];
@@ -375,7 +380,7 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const 
     }
     __syncthreads();
     uint32_t extra = 0;
-    for (uint32_t a = tid; a < K; a += kGT) {
+    for (uint32_t a = tid; a < K; a += NT) {
         const uint32_t lo = soff[a], ns = soff[a + 1] - lo;
         uint32_t code = kRelNone << 14;
         if (ns == 1) {
@@ -387,12 +392,12 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const 
         }
         nx[a] = (uint16_t)code;
     }
-    extra = block_sum(extra, S);
+    extra = block_sum<NT>(extra, S);
 
     // ---- heads of every group, and the groups waiting on every group
     uint16_t *gpend = (uint16_t *)(I.ws + L.gpend), *gloff = (uint16_t *)(I.ws + L.gloff);
     uint16_t *hdoff = (uint16_t *)(I.ws + L.hdoff), *hd = (uint16_t *)(I.ws + L.hd), *gl = (uint16_t *)(I.ws + L.gl);
-    for (uint32_t g = tid; g < G; g += kGT) {
+    for (uint32_t g = tid; g < G; g += NT) {
         uint32_t c = 0;
         for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b) c += pend[b] == 0u;
         hcnt[g] = c;
@@ -403,9 +408,9 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared &S, const 
         gcnt[g] = nw;
     }
     __syncthreads();
-    block_scan(hcnt, G, S);
-    block_scan(gcnt, G, S);
-    for (uint32_t g = tid; g <= G; g += kGT) {
+    block_scan<NT>(hcnt, G, S);
+    block_scan<NT>(gcnt, G, S);
+    for (uint32_t g = tid; g <= G; g += NT) {
         hdoff[g] = (uint16_t)hcnt[g];
         gloff[g] = (uint16_t)gcnt[g];
         if (g == G) continue;
@@ -452,7 +457,8 @@ __device__ __forceinline__ void walk_rows(int W, int sx, int sy, int dx, int dy,
 // accumulates in the workspace over the ranges it crosses.  Same results as the one-piece
 // build.  Returns false, having changed nothing the workspace build does not redo, when a
 // single row does not fit.
-__device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const Layout &L, uint32_t K, uint32_t G,
+template <int NT>
+__device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
                                             uint32_t T, uint8_t *lds, uint32_t lds_bytes)
 {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
@@ -478,21 +484,21 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
     const uint32_t tile_bytes = lds_bytes - (uint32_t)fixed;
 
     // ---- set-up; visits per row through a difference array
-    for (uint32_t g = tid; g < G; g += kGT)
+    for (uint32_t g = tid; g < G; g += NT)
         for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b) grp[b] = (uint16_t)g;
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         mv32[b] = (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
         sfill[b] = 0;
         pend[b] = 0;
     }
-    for (uint32_t b = tid; b <= K; b += kGT) soff[b] = 0;
-    for (uint32_t i = tid; i < G * GW; i += kGT) gbits[i] = 0;
-    for (int y = tid; y <= H; y += kGT) rowc[y] = 0;
+    for (uint32_t b = tid; b <= K; b += NT) soff[b] = 0;
+    for (uint32_t i = tid; i < G * GW; i += NT) gbits[i] = 0;
+    for (int y = tid; y <= H; y += NT) rowc[y] = 0;
     if (tid == 0) S.flags = 0;
     __syncthreads();
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const uint32_t nh = (uint32_t)iabs(dx - sx) + 1u;
@@ -547,17 +553,17 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
     const uint32_t R = S.nr;
 
     // ---- per-range move lists: a path's rows are contiguous, so a move lies in ranges ra..rb
-    for (uint32_t r = tid; r <= R; r += kGT) roff[r] = 0;
+    for (uint32_t r = tid; r <= R; r += NT) roff[r] = 0;
     __syncthreads();
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const uint32_t ra = rrow[min(sy, dy)], rb = rrow[max(sy, dy)];
         for (uint32_t r = ra; r <= rb; ++r) add_wg32(&roff[r], 1u);
     }
     __syncthreads();
-    block_scan(roff, R, S);
-    for (uint32_t b = tid; b < K; b += kGT) {
+    block_scan<NT>(roff, R, S);
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const uint32_t ra = rrow[min(sy, dy)], rb = rrow[max(sy, dy)];
@@ -572,17 +578,17 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         uint32_t *cell = (uint32_t *)tile;
         uint16_t *touch = (uint16_t *)(tile + 4 * ((size_t)nc + 1));
         const uint32_t mlo = r ? roff[r - 1] : 0u, mhi = roff[r];
-        for (uint32_t c = tid; c <= nc; c += kGT) cell[c] = 0;
+        for (uint32_t c = tid; c <= nc; c += NT) cell[c] = 0;
         if (tid == 0) S.nlong = 0;
         __syncthreads();
-        for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
+        for (uint32_t t = mlo + tid; t < mhi; t += NT) {
             int sx, sy, dx, dy;
             load_move(I.moves, rlist[t], sx, sy, dx, dy);
             walk_rows(W, sx, sy, dx, dy, y0, y1, [&](int c) { add_wg32(&cell[(uint32_t)c - c0], 1u); });
         }
         __syncthreads();
-        block_scan(cell, nc, S);
-        for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
+        block_scan<NT>(cell, nc, S);
+        for (uint32_t t = mlo + tid; t < mhi; t += NT) {
             const uint32_t b = rlist[t];
             int sx, sy, dx, dy;
             load_move(I.moves, b, sx, sy, dx, dy);
@@ -598,7 +604,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         // in a wave of short walks would otherwise hold the other 63 lanes.
         // Lists of kSortLo+1..128 entries (the receiver columns') are sorted first, a wave each
         // (two entries per lane, bitonic network), and searched by bisection.
-        for (uint32_t cb = (uint32_t)wid * kWave; cb < nc; cb += (uint32_t)kGT) {
+        for (uint32_t cb = (uint32_t)wid * kWave; cb < nc; cb += (uint32_t)NT) {
             const uint32_t c = cb + lane;
             uint32_t n = 0;
             if (c < nc) n = cell[c] - (c ? cell[c - 1] : 0u);
@@ -650,7 +656,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
             }
             return best;
         };
-        for (uint32_t t = mlo + tid; t < mhi; t += kGT) {
+        for (uint32_t t = mlo + tid; t < mhi; t += NT) {
             const uint32_t b = rlist[t];
             int sx, sy, dx, dy;
             load_move(I.moves, b, sx, sy, dx, dy);
@@ -703,7 +709,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         __syncthreads();
         // the queued long legs, one wave each
         const uint32_t nq = S.nlong < kLongCap ? S.nlong : kLongCap;
-        for (uint32_t qi = (uint32_t)wid; qi < nq; qi += (uint32_t)kGWaves) {
+        for (uint32_t qi = (uint32_t)wid; qi < nq; qi += (uint32_t)(NT / kWave)) {
             const uint32_t b = S.longq[qi];
             int sx, sy, dx, dy;
             load_move(I.moves, b, sx, sy, dx, dy);
@@ -765,17 +771,18 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared &S, const
         return true;
     }
     // ---- successor counts, then the common second half
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         const uint32_t np = pend[b];
         for (uint32_t i = 0; i < np; ++i) add_wg32(&soff[preds[(size_t)b * kMaxPreds + i]], 1u);
     }
     __syncthreads();
-    graph_tail(I, S, L, K, G, T);
+    graph_tail<NT>(I, S, L, K, G, T);
     return true;
 }
 
 // Build the graph of one instance (whole workgroup).  lds: dynamic LDS of lds_bytes bytes.
-__device__ void graph_build(const Inst &I, GraphShared &S, uint8_t *lds, uint32_t lds_bytes, bool force_generic)
+template <int NT>
+__device__ void graph_build(const Inst &I, GraphShared<NT / kWave> &S, uint8_t *lds, uint32_t lds_bytes, bool force_generic)
 {
     const int tid = threadIdx.x;
     const int W = I.W, H = I.H;
@@ -796,17 +803,17 @@ __device__ void graph_build(const Inst &I, GraphShared &S, uint8_t *lds, uint32_
     // ---- validate moves and groups; total steps
     bool bad = false;
     uint32_t T = 0;
-    for (uint32_t b = tid; b < K; b += kGT) {
+    for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         const int len = iabs(dx - sx) + iabs(dy - sy);
         bad |= sx >= W || dx >= W || sy >= H || dy >= H || len == 0;
         T += (uint32_t)len;
     }
-    for (uint32_t g = tid; g < G; g += kGT) bad |= I.goff[g] > I.goff[g + 1];
+    for (uint32_t g = tid; g < G; g += NT) bad |= I.goff[g] > I.goff[g + 1];
     if (tid == 0) bad |= I.goff[0] != 0 || I.goff[G] != K;
-    const uint32_t nbad = block_sum(bad ? 1u : 0u, S);
-    T = block_sum(T, S);
+    const uint32_t nbad = block_sum<NT>(bad ? 1u : 0u, S);
+    T = block_sum<NT>(T, S);
     if (nbad) {
         if (tid == 0) { put_info(I.binfo, RR_E_INVAL, 0, 0, 0, 0); hdr[H_STATE] = ST_DONE; }
         return;
@@ -828,9 +835,9 @@ __device__ void graph_build(const Inst &I, GraphShared &S, uint8_t *lds, uint32_
     if (need <= lds_bytes) {
         uint16_t *grp = (uint16_t *)(lds + 4 * ((size_t)WH + 1));
         uint16_t *touch = (uint16_t *)(lds + 4 * ((size_t)WH + 1) + 2 * (((size_t)K + 1) & ~(size_t)1));
-        graph_core(I, S, L, K, G, T, (uint32_t *)lds, grp, touch);
-    } else if (!graph_tiled(I, S, L, K, G, T, lds, lds_bytes)) {
-        graph_core(I, S, L, K, G, T, (uint32_t *)(I.ws + L.cell), (uint16_t *)(I.ws + L.grp),
+        graph_core<NT>(I, S, L, K, G, T, (uint32_t *)lds, grp, touch);
+    } else if (!graph_tiled<NT>(I, S, L, K, G, T, lds, lds_bytes)) {
+        graph_core<NT>(I, S, L, K, G, T, (uint32_t *)(I.ws + L.cell), (uint16_t *)(I.ws + L.grp),
                    (uint16_t *)(I.ws + L.touch));
     }
 }

@@ -2,10 +2,11 @@
 
 A solve call carries one schedule knob in its flags word (include/rr.h): bits 8..11, the
 wavefronts per instance (1, 2 or 4; at least one thread per grid side), i.e. how many waves
-work one shot and how many shots a CU holds.  A batching call carries two:
+work one shot and how many shots a CU holds.  A batching call carries three:
   * bits 24..31 -- the graph kernel's LDS tile budget in KiB: how much of a grid's per-trap
     lists one workgroup holds at a time, hence workgroups per CU and, for large grids, the
     number of row ranges of the tiled build;
+  * bits 20..23 -- the graph kernel's wavefronts per instance, over four (4, 8 or 16 waves);
   * bits 8..15 -- the loop kernel's LDS budget in KiB: the loop data of an instance in LDS or
     in the workspace, hence how many instance wavefronts one SIMD holds.
 Neither changes a single result bit (the batches are Alg. 3's, whatever the schedule).  The
@@ -34,14 +35,19 @@ GRAPH_KIB = (24, 32, 48, 64, 96, 128, 150)
 LOOP_KIB = (1, 4, 8, 16, 32, 64)
 DEFAULT_GRAPH_KIB, DEFAULT_LOOP_KIB = 64, 1    # the library's own many-instance budgets
 MARGIN = 0.03                                  # a candidate must beat the default by this much
-_SCHED_MASK = (0xFF << 24) | (0xFF << 8)
+GRAPH_WAVES = (4, 8, 16)                       # graph kernel wavefronts per instance
+DEFAULT_GRAPH_WAVES = 8
+_SCHED_MASK = (0xFF << 24) | (0xF << 20) | (0xFF << 8)
 
 
-def schedule_bits(graph_kib: int, loop_kib: int) -> int:
-    """Flags bits of one schedule (both budgets in KiB, 1..255)."""
+def schedule_bits(graph_kib: int, loop_kib: int, graph_waves: int = 0) -> int:
+    """Flags bits of one schedule (both budgets in KiB, 1..255; graph wavefronts per instance
+    4, 8 or 16, 0 for the library's default)."""
     if not (1 <= graph_kib <= 255 and 1 <= loop_kib <= 255):
         raise ValueError("LDS budgets are 1..255 KiB")
-    return (int(graph_kib) << 24) | (int(loop_kib) << 8)
+    if graph_waves not in (0, 4, 8, 16):
+        raise ValueError("graph wavefronts per instance are 4, 8 or 16")
+    return (int(graph_kib) << 24) | ((int(graph_waves) // 4) << 20) | (int(loop_kib) << 8)
 
 
 def solve_flags_for(size_class: int, algo: int = 0, table: dict | None = None) -> int:
@@ -87,7 +93,7 @@ def flags_for(size_class: int, flags: int = 0, table: dict | None = None) -> int
     e = table["classes"].get(str(int(size_class)))
     if not e:
         return flags
-    return flags | schedule_bits(e["graph_kib"], e["loop_kib"])
+    return flags | schedule_bits(e["graph_kib"], e["loop_kib"], int(e.get("graph_waves", 0)))
 
 
 def loop_lds_floor(side: int) -> int:
@@ -197,16 +203,24 @@ def tune_class(mb, constraint: int = 0, graph_kib=GRAPH_KIB, loop_kib=LOOP_KIB, 
             raise RuntimeError(f"graph budget {g} KiB changed the batching outputs")
         gt[int(g)] = t
     best_g = _pick(gt, DEFAULT_GRAPH_KIB)
+    wt = {}
+    for gw in GRAPH_WAVES:
+        t, _, out = _run(mb, constraint | (int(best_g) << 24) | ((int(gw) // 4) << 20), reps)
+        if not _same(out, ref):
+            raise RuntimeError(f"{gw} graph wavefronts per instance changed the batching outputs")
+        wt[int(gw)] = t
+    best_w = _pick(wt, DEFAULT_GRAPH_WAVES)
     lt = {}
     from .pipeline import size_class
     side = max(size_class(s) for s in mb.shapes)
     for lk in _distinct_loop_budgets(side, loop_kib):
-        _, t, out = _run(mb, constraint | schedule_bits(best_g, lk), reps)
+        _, t, out = _run(mb, constraint | schedule_bits(best_g, lk, best_w), reps)
         if not _same(out, ref):
             raise RuntimeError(f"loop budget {lk} KiB changed the batching outputs")
         lt[int(lk)] = t
     best_l = _pick(lt, DEFAULT_LOOP_KIB)
-    return {"graph_kib": best_g, "loop_kib": best_l, "graph_ms": round(gt[best_g], 3),
+    return {"graph_kib": best_g, "graph_waves": best_w, "loop_kib": best_l, "graph_ms": round(wt[best_w], 3),
+            "graph_ms_by_waves": {str(k): round(v, 3) for k, v in wt.items()},
             "loop_ms": round(lt[best_l], 3), "graph_ms_by_kib": {str(k): round(v, 3) for k, v in gt.items()},
             "loop_ms_by_kib": {str(k): round(v, 3) for k, v in lt.items()}, "shots": mb.n}
 

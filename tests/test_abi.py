@@ -98,3 +98,11 @@ def test_solve_waves_per_instance_checked_before_launch():
         assert rc == rr.RR_E_INVAL, (shape, waves)
     rc = rr.rr_solve_many(1, 8, 200, 200, 8, 8, 8, 8, 8, 2 << 8, None, 0, stream=0, check=False)
     assert rc == rr.RR_E_INVAL
+
+
+def test_batch_graph_waves_checked_before_launch():
+    shape = (32, 32, 8, 8, 24, 24)
+    need = rr.rr_batch_workspace_bytes(shape, 100, 100)
+    for bad in (1 << 17, 3 << 20, 15 << 20):
+        rc = rr.rr_batch_moves(shape, 8, 8, 8, 100, bad, 8, 100, 8, 100, 8, 8, need, stream=0, check=False)
+        assert rc == rr.RR_E_INVAL, hex(bad)

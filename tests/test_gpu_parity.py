@@ -296,7 +296,8 @@ def test_fast_path_equals_general_path_and_lds_budgets():
     workspace (2 KiB: below one tile); the smaller grids also against the oracle."""
     shots = ri.config_shots("mixed", n=21) + ri.config_shots("batch64", n=6)
     variants = {"general": GENERIC, "loop in LDS": 64 << 8, "graph in 12 KiB tiles": 12 << 24,
-                "graph in the workspace": 2 << 24}
+                "graph in the workspace": 2 << 24, "graph on 4 wavefronts per instance": (64 << 24) | (1 << 20),
+                "graph on 16 wavefronts per instance": (64 << 24) | (4 << 20)}
     for flags in (0, 1, 2):
         say("case paths flags", flags)
         ref, shapes, grids = run_many(shots, flags)
