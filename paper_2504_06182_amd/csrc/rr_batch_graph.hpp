@@ -233,18 +233,73 @@ __device__ __forceinline__ void sort_list(uint16_t *a, int n)
     }
 }
 
-// add v to the small distinct set s[0..n) (n <= kMaxPreds); sets ovf when it is full
-__device__ __forceinline__ void set_add(uint32_t (&s)[kMaxPreds], int &n, uint32_t v, bool &ovf)
+// packed coordinates sx | sy << 8 | dx << 16 | dy << 24 of move b
+__device__ __forceinline__ uint32_t packed_move(const rr_move *mv, uint32_t b)
+{
+    int sx, sy, dx, dy;
+    load_move(mv, b, sx, sy, dx, dy);
+    return (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
+}
+
+__device__ __forceinline__ bool spans(int v, int a, int b) { return a <= b ? (a <= v && v <= b) : (b <= v && v <= a); }
+
+__device__ __forceinline__ bool overlap(int a1, int b1, int a2, int b2)
+{
+    const int lo1 = a1 < b1 ? a1 : b1, hi1 = a1 < b1 ? b1 : a1, lo2 = a2 < b2 ? a2 : b2, hi2 = a2 < b2 ? b2 : a2;
+    return (lo1 > lo2 ? lo1 : lo2) <= (hi1 < hi2 ? hi1 : hi2);
+}
+
+// Do the paths of two moves (packed coordinates) share a trap?  A path runs along row sy from sx
+// to dx, then along column dx from sy to dy, endpoints included.
+__device__ __forceinline__ bool paths_meet(uint32_t p, uint32_t q)
+{
+    const int psx = p & 0xFF, psy = (p >> 8) & 0xFF, pdx = (p >> 16) & 0xFF, pdy = p >> 24;
+    const int qsx = q & 0xFF, qsy = (q >> 8) & 0xFF, qdx = (q >> 16) & 0xFF, qdy = q >> 24;
+    const bool hh = psy == qsy && overlap(psx, pdx, qsx, qdx);
+    const bool hv = spans(qdx, psx, pdx) && spans(psy, qsy, qdy);     // p's row leg, q's column leg
+    const bool vh = spans(pdx, qsx, qdx) && spans(qsy, psy, pdy);     // p's column leg, q's row leg
+    const bool vv = pdx == qdx && overlap(psy, pdy, qsy, qdy);
+    return hh || hv || vh || vv;
+}
+
+// Add in-group predecessor v (packed coordinates vc) to the set s[0..n) of one move (packed
+// coordinates in pc), keeping the set free of redundant members: two moves of one group whose
+// paths meet are joined by an edge of the dependency graph (the earlier precedes the later), so
+// of two members whose paths meet the earlier is an ancestor of the later and adds nothing to
+// the move's readiness.  Such earlier members are dropped (v too, when a later member meets it);
+// readiness, hence every batch, is unchanged.  Sets ovf when a needed member does not fit.
+__device__ __forceinline__ void pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc)[kMaxPreds], int &n, uint32_t v,
+                                         uint32_t vc, bool &ovf)
 {
     bool have = false;
 #pragma unroll
     for (int i = 0; i < kMaxPreds; ++i) have |= (i < n) && s[i] == v;
     if (have) return;
-    if (n == kMaxPreds) { ovf = true; return; }
+    bool redundant = false;
+    uint32_t ks[kMaxPreds], kc[kMaxPreds];
+    int m = 0;
 #pragma unroll
-    for (int i = 0; i < kMaxPreds; ++i)
-        if (i == n) s[i] = v;
-    ++n;
+    for (int i = 0; i < kMaxPreds; ++i) {
+        ks[i] = 0; kc[i] = 0;
+        if (i >= n) continue;
+        const bool meet = paths_meet(pc[i], vc);
+        redundant |= meet && s[i] > v;
+        const bool keep = !(meet && s[i] < v);
+#pragma unroll
+        for (int j = 0; j < kMaxPreds; ++j)
+            if (keep && j == m) { ks[j] = s[i]; kc[j] = pc[i]; }
+        m += keep ? 1 : 0;
+    }
+    if (!redundant) {
+        if (m == kMaxPreds) { ovf = true; return; }
+#pragma unroll
+        for (int j = 0; j < kMaxPreds; ++j)
+            if (j == m) { ks[j] = v; kc[j] = vc; }
+        ++m;
+    }
+#pragma unroll
+    for (int i = 0; i < kMaxPreds; ++i) { s[i] = ks[i]; pc[i] = kc[i]; }
+    n = m;
 }
 
 template <int NT>
@@ -315,7 +370,7 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         load_move(I.moves, b, sx, sy, dx, dy);
         const int len = iabs(dx - sx) + iabs(dy - sy);
         const uint32_t g = grp[b];
-        uint32_t ps[kMaxPreds];
+        uint32_t ps[kMaxPreds], pc[kMaxPreds];
         int np = 0;
         bool ovf = false;
         uint32_t last = 0xFFFFFFFFu, lastg = 0xFFFFFFFFu;
@@ -332,7 +387,7 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
             last = a;
             const uint32_t ga = grp[a];
             if (ga == g) {
-                set_add(ps, np, a, ovf);
+                pred_add(ps, pc, np, a, packed_move(I.moves, a), ovf);
             } else if (ga != lastg) {        // a group predecessor: the bit matrix keeps it once
                 lastg = ga;
                 __hip_atomic_fetch_or(&gbits[g * GW + ga / 32], 1u << (ga & 31), __ATOMIC_RELAXED,
@@ -666,7 +721,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
                 const uint32_t at = add_wg32(&S.nlong, 1u);
                 if (at < kLongCap) { S.longq[at] = (uint16_t)b; defer = true; }
             }
-            uint32_t ps[kMaxPreds];
+            uint32_t ps[kMaxPreds], pc[kMaxPreds];
             int np = 0;
             bool loaded = false, changed = false, ovf = false;
             uint32_t last = 0xFFFFFFFFu, lastg = 0xFFFFFFFFu;
@@ -683,12 +738,11 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
                         np = (int)pend[b];
 #pragma unroll
                         for (int i = 0; i < kMaxPreds; ++i)
-                            if (i < np) ps[i] = preds[(size_t)b * kMaxPreds + i];
+                            if (i < np) { ps[i] = preds[(size_t)b * kMaxPreds + i]; pc[i] = packed_move(I.moves, ps[i]); }
                         loaded = true;
                     }
-                    const int before = np;
-                    set_add(ps, np, a, ovf);
-                    changed |= np != before;
+                    pred_add(ps, pc, np, a, packed_move(I.moves, a), ovf);
+                    changed = true;
                 } else {
                     const uint32_t ga = grp[a];
                     if (ga != lastg) {
@@ -715,7 +769,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
             load_move(I.moves, b, sx, sy, dx, dy);
             const uint32_t g = grp[b], glo = I.goff[g];
             const int nh = iabs(dx - sx) + 1, sth = dx >= sx ? 1 : -1;
-            uint32_t ps[kMaxPreds];
+            uint32_t ps[kMaxPreds], pc[kMaxPreds];
             int np = 0;
             bool loaded = false, changed = false, ovf = false;
             uint32_t lastg = 0xFFFFFFFFu;
@@ -739,12 +793,11 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
                             np = (int)pend[b];
 #pragma unroll
                             for (int i = 0; i < kMaxPreds; ++i)
-                                if (i < np) ps[i] = preds[(size_t)b * kMaxPreds + i];
+                                if (i < np) { ps[i] = preds[(size_t)b * kMaxPreds + i]; pc[i] = packed_move(I.moves, ps[i]); }
                             loaded = true;
                         }
-                        const int before = np;
-                        set_add(ps, np, u, ovf);
-                        changed |= np != before;
+                        pred_add(ps, pc, np, u, packed_move(I.moves, u), ovf);
+                        changed = true;
                     } else {
                         const uint32_t gu = (uint32_t)__builtin_amdgcn_readlane((int)ga, l);
                         if (gu != lastg) {
