@@ -257,8 +257,35 @@ def loop(Gd, S, flags):
     return np.array(boff, np.uint32), np.array(steps, np.uint32), st
 
 
-def graph(shape, moves, goff):
-    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other."""
+def paths_meet(p, q):
+    """Do the H-then-V paths of moves p, q = (sx, sy, dx, dy) share a trap (paths_meet)?"""
+    def spans(v, a, b): return min(a, b) <= v <= max(a, b)
+    def overlap(a1, b1, a2, b2): return max(min(a1, b1), min(a2, b2)) <= min(max(a1, b1), max(a2, b2))
+    psx, psy, pdx, pdy = p; qsx, qsy, qdx, qdy = q
+    return ((psy == qsy and overlap(psx, pdx, qsx, qdx)) or (spans(qdx, psx, pdx) and spans(psy, qsy, qdy))
+            or (spans(pdx, qsx, qdx) and spans(qsy, psy, pdy)) or (pdx == qdx and overlap(psy, pdy, qsy, qdy)))
+
+
+def pred_add(ps, a, mvs, reduce=True):
+    """Add in-group predecessor a to the list ps as pred_add does: members whose paths meet a's
+    and that come before a are dropped, a is not added when a later member's path meets it.
+    Returns True when a needed member did not fit (8 at most).  reduce=False keeps every
+    distinct member, without that limit (the unreduced sets, for comparison)."""
+    if a in ps: return False
+    if not reduce:
+        ps.append(a)
+        return False
+    red = any(u > a and paths_meet(mvs[u], mvs[a]) for u in ps)
+    ps[:] = [u for u in ps if not (u < a and paths_meet(mvs[u], mvs[a]))]
+    if red: return False
+    if len(ps) == 8: return True
+    ps.append(a)
+    return False
+
+
+def graph(shape, moves, goff, reduce=True):
+    """Transliteration of graph_core (rr_batch_graph.hpp), threads run one after the other.
+    reduce=False keeps every distinct in-group previous toucher (no pred_add reduction, no limit)."""
     W, H = shape[0], shape[1]
     K = len(moves); G = len(goff) - 1; WH = W * H
     mvs = [tuple(int(v) for v in m) for m in moves]
@@ -303,9 +330,7 @@ def graph(shape, moves, goff):
             if a == last: continue
             last = a
             if grp[a] == g:
-                if a not in ps:
-                    if len(ps) == 8: ovf = True
-                    else: ps.append(a)
+                ovf |= pred_add(ps, a, mvs, reduce)
             else:
                 if grp[a] not in gs: gs.append(grp[a])
         pend[b] = len(ps); preds[b] = ps
@@ -356,7 +381,7 @@ def walk_rows(W, m, y0, y1):
     return out
 
 
-def graph_tiled(shape, moves, goff, tile_bytes):
+def graph_tiled(shape, moves, goff, tile_bytes, reduce=True):
     """The tiled build (graph_tiled, rr_batch_graph.hpp) step by step: row counts through a
     difference array, greedy row ranges of at most 64 rows whose cells (4 B + 4) and visits (2 B)
     fit tile_bytes, per-range move lists, then per range the touch lists and previous touchers
@@ -418,9 +443,7 @@ def graph_tiled(shape, moves, goff, tile_bytes):
                 if a == last: continue
                 last = a
                 if a >= glo:
-                    if a not in preds[b]:
-                        if len(preds[b]) == 8: ovf = True
-                        else: preds[b].append(a)
+                    ovf |= pred_add(preds[b], a, mvs, reduce)
                 elif grp[a] != lastg:
                     lastg = grp[a]
                     gbits.setdefault(g, set()).add(grp[a])

@@ -15,13 +15,14 @@ def _cases():
         for d in ri.config_shots(name, n=n):
             if d["w"] <= 64:
                 out.append((name, d))
+    out += [("bird", d) for d in ri.config_shots("batch64", n=2)]
     return out
 
 
 @pytest.mark.parametrize("name,d", _cases(), ids=lambda v: v if isinstance(v, str) else f"shot{v['shot']}")
 def test_model_matches_oracle(name, d):
     shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
-    r = oracle.solve(shape, ri.shot_grid(d))
+    r = oracle.solve(shape, ri.shot_grid(d), bird=(name == "bird"))
     assert r["status"] == 0
     g = M.graph(shape, r["moves"], r["group_off"])
     S = 3
@@ -65,16 +66,39 @@ def test_ready_set_overflow_fixture():
         assert np.array_equal(pb, b["batch_off"]) and np.array_equal(ps, b["steps"]), flags
 
 
+def ancestors(preds):
+    """In-group ancestors of every move through the predecessor sets (moves in index order)."""
+    anc = []
+    for b, ps in enumerate(preds):
+        s = set()
+        for a in ps:
+            assert a < b
+            s |= anc[a] | {a}
+        anc.append(s)
+    return anc
+
+
+def preds_of(g):
+    want = [set() for _ in range(g["K"])]
+    for a, ss in enumerate(g["succ"]):
+        for b in ss:
+            want[b].add(a)
+    return want
+
+
 @pytest.mark.parametrize("tile_kib", [60, 12, 3])
-def test_tiled_graph_equals_one_piece(tile_kib):
+@pytest.mark.parametrize("bird", [False, True], ids=["redrec", "bird"])
+def test_tiled_graph_equals_one_piece(tile_kib, bird):
     """The tiled graph build (row ranges in LDS, per-move predecessor sets accumulated over the
-    ranges) gives the one-piece build's predecessor sets and group bit matrix, with few or many
-    ranges; a budget below one row falls back."""
+    ranges) gives the one-piece build's group bit matrix and, through its predecessor sets, the
+    same in-group ancestors as the one-piece build and as the unreduced sets (the reduced sets
+    may differ in which redundant member they keep, with ranges arriving in another order), with
+    few or many ranges; a budget below one row falls back."""
     shots = [d for d in ri.config_shots("mixed", n=12) if d["w"] <= 96][:4] + ri.config_shots("batch64", n=1)
     most = 0
     for d in shots:
         shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
-        r = oracle.solve(shape, ri.shot_grid(d))
+        r = oracle.solve(shape, ri.shot_grid(d), bird=bird)
         if r["status"] != 0 or len(r["moves"]) == 0:
             continue
         g = M.graph(shape, r["moves"], r["group_off"])
@@ -83,11 +107,12 @@ def test_tiled_graph_equals_one_piece(tile_kib):
             assert tile_kib == 3
             continue
         preds, gbits, R = t
-        want = [set() for _ in range(g["K"])]
-        for a, ss in enumerate(g["succ"]):
-            for b in ss:
-                want[b].add(a)
-        assert preds == want
+        want = preds_of(g)
+        full = preds_of(M.graph(shape, r["moves"], r["group_off"], reduce=False))
+        assert ancestors(preds) == ancestors(want) == ancestors(full)
+        if tile_kib == 60:
+            full_t, _, _ = M.graph_tiled(shape, r["moves"], r["group_off"], tile_kib * 1024, reduce=False)
+            assert full_t == full
         wantg = {}
         for h, ws in enumerate(g["gw"]):
             for x in ws:
@@ -108,3 +133,44 @@ def test_tiled_graph_long_row_fixture():
     assert R > 1 and gbits == {}
     assert preds == [set()] + [{b - 1} for b in range(1, len(mv))]
     assert [len(s) for s in g["succ"]] == [1] * (len(mv) - 1) + [0]
+
+
+def test_paths_meet_is_trap_intersection():
+    """paths_meet (the O(1) test the graph build reduces predecessor sets with) says whether two
+    H-then-V paths share a trap, checked against the traps of both paths on random moves, short
+    and degenerate ones included."""
+    rng = np.random.default_rng(11)
+
+    def traps(m):
+        sx, sy, dx, dy = m
+        st = 1 if dx >= sx else -1
+        out = {(x, sy) for x in range(sx, dx + st, st)}
+        st = 1 if dy >= sy else -1
+        return out | {(dx, y) for y in range(sy, dy + st, st)}
+
+    n_meet = 0
+    for _ in range(20000):
+        p, q = (tuple(int(v) for v in rng.integers(0, 9, 4)) for _ in range(2))
+        want = bool(traps(p) & traps(q))
+        assert M.paths_meet(p, q) == want == M.paths_meet(q, p), (p, q)
+        n_meet += want
+    assert 2000 < n_meet < 18000
+
+
+def test_reduced_sets_keep_bird_within_register_sets():
+    """Bird's moves have more distinct in-group previous touchers than the 8 a set holds; after
+    the reduction no member's path meets another's and at most one remains on these shots, while
+    readiness (in-group ancestors) is that of the unreduced sets."""
+    most_full = 0
+    for d in ri.config_shots("batch64", n=3):
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        r = oracle.solve(shape, ri.shot_grid(d), bird=True)
+        mv = [tuple(int(v) for v in m) for m in r["moves"]]
+        red = preds_of(M.graph(shape, r["moves"], r["group_off"]))
+        full = preds_of(M.graph(shape, r["moves"], r["group_off"], reduce=False))
+        most_full = max(most_full, max(len(p) for p in full))
+        assert max(len(p) for p in red) <= 1
+        assert ancestors(red) == ancestors(full)
+        for ps in red:
+            assert not any(M.paths_meet(mv[a], mv[b]) for a in ps for b in ps if a < b)
+    assert most_full > 8
