@@ -98,17 +98,23 @@ typedef struct {
 #define RR_BIRD            2u
 /* Wavefronts per instance of the solve kernels (flags bits 8..11): 1, 2 or 4 (0 = the default,
  * 4).  A launch needs at least one thread per grid side: 64 * waves >= the largest side of the
- * call's grids, else the call returns RR_E_INVAL.  A schedule knob: results do not depend on
- * it. */
+ * call's grids up to RR_LDS_SIDE, else the call returns RR_E_INVAL.  Grids beyond RR_LDS_SIDE
+ * always run 16 wavefronts (rr_solve then wants 0 in this field).  A schedule knob: results do
+ * not depend on it. */
 #define RR_SOLVE_WAVES(n)  ((uint32_t)(n) << 8)
 
 /* Largest grid side the device kernels take. */
-#define RR_MAX_SIDE 256u
+#define RR_MAX_SIDE 1024u
+/* Largest grid side whose per-instance state stays in LDS.  Larger grids run the wide kernels:
+ * the solve keeps its state in the caller's workspace (rr_solve_workspace_bytes), and batching
+ * runs a path of its own (rr_batch_moves). */
+#define RR_LDS_SIDE 256u
 
 /* ------------------------------------------------------------------------------------------ */
 /* Single instance                                                                             */
 
-/* Bytes of device workspace rr_solve needs for this shape (0: none). */
+/* Bytes of device workspace rr_solve needs for this shape: 0 up to RR_LDS_SIDE per side, about
+ * 0.75 MiB beyond.  The workspace must be 256-byte aligned. */
 size_t rr_solve_workspace_bytes(rr_shape shape);
 
 /* Solve one instance with red-rec (§III.C-D, Alg. 1).
@@ -198,8 +204,12 @@ typedef struct {
  * moves/group offsets/final bit rows at its offsets and infos[i].  Results are bit-identical to
  * n calls of rr_solve with the same flags (the algorithm, as in rr_solve).  max_w / max_h
  * bound every instance's grid (they pick the kernel variant; an instance beyond them gets
- * RR_E_INVAL).  workspace / workspace_bytes: n * rr_solve_workspace_bytes of the largest grid
- * (0 for grids up to RR_MAX_SIDE: NULL is then accepted). */
+ * RR_E_INVAL).  workspace / workspace_bytes: n * rr_solve_workspace_bytes of a grid beyond
+ * RR_LDS_SIDE when max_w or max_h is beyond it (instance i uses the i-th such slice), else
+ * nothing (NULL is then accepted); too little gives RR_E_NOMEM.  With max_w or max_h beyond
+ * RR_LDS_SIDE the call launches two kernels, one for the instances beyond RR_LDS_SIDE, one for
+ * the others; the wavefront field of flags applies to the latter and must give at least 256
+ * threads. */
 rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max_w, uint32_t max_h,
                         const uint64_t *occ_arena, rr_move *move_arena, uint32_t *group_arena,
                         uint64_t *final_arena, rr_solve_info *infos, uint32_t flags,

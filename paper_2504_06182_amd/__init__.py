@@ -18,7 +18,8 @@ RR_E_INVAL, RR_E_CAPACITY, RR_E_DEVICE, RR_E_NOMEM, RR_E_INTERNAL, RR_E_UNSUPPOR
 RR_LAMBDA_LINE_OR_COL, RR_LAMBDA_ALONG, RR_LAMBDA_NONE = 0, 1, 2
 RR_REDREC_PARALLEL, RR_REDREC_SERIAL, RR_BIRD = 0, 1, 2
 RR_BATCH_GENERIC = 1 << 16
-RR_MAX_SIDE = 256
+RR_MAX_SIDE = 1024
+RR_LDS_SIDE = 256
 RR_MAX_CHAIN = 65535
 RR_NOALLOC_WORKSPACE_BYTES = 64 << 20
 STATUS_NAMES = {0: "RR_OK", 1: "RR_INFEASIBLE", -1: "RR_E_INVAL", -2: "RR_E_CAPACITY", -3: "RR_E_DEVICE",

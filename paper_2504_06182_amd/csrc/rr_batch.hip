@@ -11,12 +11,16 @@
 //               graphs, a ready set that outgrew the registers during the loop, which then
 //               hands the instance over) -- every other wave exits.
 // Each instance's status moves through a header word in its workspace, so the three launches
-// need no host round trip.  Results do not depend on which path ran.
+// need no host round trip.  Results do not depend on which path ran.  Grids beyond RR_LDS_SIDE
+// run the wide path instead (rr_batch_wide.hip: its own graph and loop kernels); a
+// many-instance launch whose bounds admit such grids runs both, each skipping the other's
+// instances.
 #include "rr_device.hpp"
 #include "rr.h"
 #include "rr_batch_generic.hpp"
 #include "rr_batch_graph.hpp"
 #include "rr_batch_common.hpp"
+#include "rr_batch_wide.hpp"
 
 #include <atomic>
 #include <mutex>
@@ -46,6 +50,7 @@ __global__ __launch_bounds__(NT) void k_graph_many(const rr_desc *__restrict__ d
     __shared__ fast::GraphShared<NT / kWave> S;
     const uint32_t i = blockIdx.x;
     const rr_desc d = desc[i];
+    if (wide_instance(d.shape, maxw, maxh)) return;
     if (!desc_usable(d, maxw, maxh, ws_bytes)) {
         if (threadIdx.x == 0) {
             const rr_solve_info si = sinfos[i];
@@ -132,7 +137,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_many(uint32_t n, rr_desc 
             uint32_t sc = (si.status == RR_OK && si.n_steps > 0) ? si.n_steps : 1u;
             v[0] = sc;
             v[1] = (uint64_t)sc + 1;
-            v[2] = fast::al256(fast::layout(d.shape.w, d.shape.h, d.move_cap, sc).total);
+            v[2] = wide::wide_shape(d.shape.w, d.shape.h) ? wide::al256(wide::layout(d.shape.w, d.shape.h, d.move_cap).total)
+                                                           : fast::al256(fast::layout(d.shape.w, d.shape.h, d.move_cap, sc).total);
         }
         uint64_t incl[3];
 #pragma unroll
@@ -269,6 +275,7 @@ extern "C" rr_status rr_plan_many(uint32_t n, rr_desc *desc, const rr_solve_info
 
 extern "C" size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step_cap)
 {
+    if (wide::wide_shape(shape.w, shape.h)) return wide::layout(shape.w, shape.h, move_cap).total;
     return fast::layout(shape.w, shape.h, move_cap, step_cap).total;
 }
 
@@ -292,8 +299,12 @@ extern "C" rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const 
     I.move_cap = move_cap; I.step_cap = step_cap; I.batch_cap = batch_cap;
     I.boff = batch_off; I.steps = steps; I.binfo = binfo;
     I.ws = (uint8_t *)workspace;
-    const Plan P = make_plan(flags, shape.w, shape.h, true);
     hipStream_t st = (hipStream_t)stream;
+    if (wide::wide_shape(shape.w, shape.h)) {
+        if (((uintptr_t)workspace & 255u) != 0) return RR_E_INVAL;
+        return wide::launch_one(I, flags, st) == hipSuccess ? RR_OK : RR_E_DEVICE;
+    }
+    const Plan P = make_plan(flags, shape.w, shape.h, true);
     if (P.graph_threads == 256u)
         hipLaunchKernelGGL(k_graph_one<256>, dim3(1), dim3(256), P.graph_lds, st, I, P.graph_lds, flags);
     else if (P.graph_threads == 1024u)
@@ -331,9 +342,15 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     if (!batch_flags_valid(flags) || max_w < 1 || max_h < 1) return RR_E_INVAL;
     if (max_w > RR_MAX_SIDE || max_h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
     if (((uintptr_t)move_arena & 7u) != 0) return RR_E_INVAL;
-    const Plan P = make_plan(flags, max_w, max_h, false);
     hipStream_t st = (hipStream_t)stream;
     uint8_t *ws = (uint8_t *)workspace;
+    const bool wide_too = max_w > RR_LDS_SIDE || max_h > RR_LDS_SIDE;
+    if (wide_too && wide::launch_graph_many(n, desc, (int)max_w, (int)max_h, move_arena, group_arena, sinfos,
+                                            batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes,
+                                            st) != hipSuccess)
+        return RR_E_DEVICE;
+    const Plan P = make_plan(flags, max_w < RR_LDS_SIDE ? max_w : RR_LDS_SIDE, max_h < RR_LDS_SIDE ? max_h : RR_LDS_SIDE,
+                             false);
 #define RR_GRAPH_MANY(NT)                                                                                          \
     hipLaunchKernelGGL(k_graph_many<NT>, dim3(n), dim3(NT), P.graph_lds, st, desc, (int)max_w, (int)max_h,          \
                        move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes, \
@@ -343,6 +360,10 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     else RR_GRAPH_MANY(512);
 #undef RR_GRAPH_MANY
     if (graph_done_event && hipEventRecord((hipEvent_t)graph_done_event, st) != hipSuccess) return RR_E_DEVICE;
+    if (wide_too && wide::launch_loop_many(n, desc, (int)max_w, (int)max_h, move_arena, group_arena, sinfos,
+                                           batch_arena, step_arena, binfos, ws, (uint64_t)workspace_bytes, flags,
+                                           st) != hipSuccess)
+        return RR_E_DEVICE;
 #define RR_LOOP_MANY(SS, FF)                                                                                       \
     hipLaunchKernelGGL((k_loop_many<SS, FF>), dim3(n), dim3(kWave), P.loop_lds, st, desc, (int)max_w, (int)max_h,  \
                        move_arena, group_arena, sinfos, batch_arena, step_arena, binfos, ws,                       \
@@ -412,7 +433,7 @@ extern "C" rr_status rr_batch_moves_noalloc(rr_shape shape, const rr_move *moves
     if (!(shape.w >= 1 && shape.h >= 1 && shape.x0 < shape.x1 && shape.x1 <= shape.w && shape.y0 < shape.y1 &&
           shape.y1 <= shape.h))
         return RR_E_INVAL;
-    if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
+    if (shape.w > RR_LDS_SIDE || shape.h > RR_LDS_SIDE) return RR_E_UNSUPPORTED;
     if (rr_batch_workspace_bytes(shape, move_cap, step_cap) > (size_t)RR_NOALLOC_WORKSPACE_BYTES) return RR_E_NOMEM;
     void *ws = scratch_for_current_device();
     if (!ws) return RR_E_DEVICE;

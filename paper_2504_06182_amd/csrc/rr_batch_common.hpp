@@ -11,11 +11,18 @@ namespace rr {
 
 constexpr uint32_t kFlagGeneric = 1u << 16;
 
-// shape check of a many-instance descriptor
+// shape check of a many-instance descriptor for the kernels of grids up to RR_LDS_SIDE
 __device__ __forceinline__ bool shape_usable(const rr_shape s, int maxw, int maxh)
 {
-    return s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= RR_MAX_SIDE && s.h <= RR_MAX_SIDE &&
+    return s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= RR_LDS_SIDE && s.h <= RR_LDS_SIDE &&
            s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
+}
+
+// an instance of the wide kernels (rr_batch_wide.hip) in a launch whose bounds admit it: the
+// kernels of the smaller grids leave it alone
+__device__ __forceinline__ bool wide_instance(const rr_shape s, int maxw, int maxh)
+{
+    return (s.w > RR_LDS_SIDE || s.h > RR_LDS_SIDE) && s.w <= maxw && s.h <= maxh;
 }
 
 // the instance's workspace region [ws_off, ws_off + layout total) is 256-byte aligned and lies

@@ -1,4 +1,6 @@
-// rr_solve.hip -- red-rec solve on gfx950: one 256-thread workgroup (4 wave64) per instance.
+// rr_solve.hip -- red-rec solve on gfx950: one workgroup per instance, 1 to 4 wave64 for grids
+// up to 256 per side (state in LDS), 16 wave64 for larger grids up to 1024 per side (the same
+// state in a per-instance region of the caller's workspace, served by L2).
 //
 // Method (arXiv 2504.06182): exact 1D on lines (§III.A), red-rec with every column of
 // non-negative surplus solved from the outset and donor/receiver pairs identified one after the
@@ -965,6 +967,18 @@ __global__ __launch_bounds__(T) void k_solve_one(SolveArgs A)
     solve_one<S, T>(L, A);
 }
 
+// Grids beyond RR_LDS_SIDE: the instance's state lives in the workspace (same layout).
+constexpr int kWideSide = (int)RR_MAX_SIDE, kWideThreads = 1024;
+using WideLds = SolveLds<kWideSide, kWideThreads / kWave>;
+constexpr size_t kWideBytes = (sizeof(WideLds) + 255) & ~(size_t)255;
+
+__device__ __forceinline__ bool wide_shape(const rr_shape s) { return s.w > RR_LDS_SIDE || s.h > RR_LDS_SIDE; }
+
+__global__ __launch_bounds__(kWideThreads) void k_solve_wide_one(SolveArgs A, uint8_t *ws)
+{
+    solve_one<kWideSide, kWideThreads>(*reinterpret_cast<WideLds *>(ws), A);
+}
+
 template <int S, int T>
 __global__ __launch_bounds__(T) void k_solve_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                   const uint64_t *occ, rr_move *mv, uint32_t *ga,
@@ -975,6 +989,7 @@ __global__ __launch_bounds__(T) void k_solve_many(const rr_desc *__restrict__ de
     const rr_shape s = d.shape;
     const bool ok = s.w >= 1 && s.h >= 1 && s.w <= maxw && s.h <= maxh && s.w <= S && s.h <= S &&
                     s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
+    if (!ok && wide_shape(s) && s.w <= maxw && s.h <= maxh) return;   // k_solve_wide_many's instance
     if (!ok) {
         if (threadIdx.x == 0) {
             rr_solve_info inf = {RR_E_INVAL, 0u, 0u, 0u, 0u, 0u};
@@ -995,6 +1010,37 @@ __global__ __launch_bounds__(T) void k_solve_many(const rr_desc *__restrict__ de
     solve_one<S, T>(L, A);
 }
 
+// instances beyond RR_LDS_SIDE of a many-instance launch; instance i's state at ws + i * kWideBytes
+__global__ __launch_bounds__(kWideThreads) void k_solve_wide_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
+                                                                  const uint64_t *occ, rr_move *mv, uint32_t *ga,
+                                                                  uint64_t *fa, rr_solve_info *infos, uint32_t flags,
+                                                                  uint8_t *ws)
+{
+    const rr_desc d = desc[blockIdx.x];
+    const rr_shape s = d.shape;
+    if (!wide_shape(s)) return;                                       // the LDS launch's instance
+    const bool ok = s.w <= maxw && s.h <= maxh && s.w <= kWideSide && s.h <= kWideSide && s.x0 < s.x1 &&
+                    s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
+    if (!ok) {
+        if (threadIdx.x == 0) {
+            rr_solve_info inf = {RR_E_INVAL, 0u, 0u, 0u, 0u, 0u};
+            infos[blockIdx.x] = inf;
+        }
+        return;
+    }
+    SolveArgs A;
+    A.W = s.w; A.H = s.h; A.x0 = s.x0; A.y0 = s.y0; A.x1 = s.x1; A.y1 = s.y1;
+    A.flags = flags;
+    A.occ = occ + d.occ_off;
+    A.moves = mv + d.move_off;
+    A.move_cap = d.move_cap;
+    A.goff = ga + d.group_off;
+    A.group_cap = d.group_cap;
+    A.fin = fa + d.occ_off;
+    A.info = infos + blockIdx.x;
+    solve_one<kWideSide, kWideThreads>(*reinterpret_cast<WideLds *>(ws + (size_t)blockIdx.x * kWideBytes), A);
+}
+
 }  // namespace rr
 
 using namespace rr;
@@ -1004,7 +1050,10 @@ static bool shape_valid(const rr_shape &s)
     return s.w >= 1 && s.h >= 1 && s.x0 < s.x1 && s.x1 <= s.w && s.y0 < s.y1 && s.y1 <= s.h;
 }
 
-extern "C" size_t rr_solve_workspace_bytes(rr_shape) { return 0; }
+extern "C" size_t rr_solve_workspace_bytes(rr_shape shape)
+{
+    return (shape.w > RR_LDS_SIDE || shape.h > RR_LDS_SIDE) ? kWideBytes : 0;
+}
 
 // flags: bits 0..7 the algorithm, bits 8..11 wavefronts per instance (0: the default, 4)
 static bool flags_valid(uint32_t flags)
@@ -1037,7 +1086,6 @@ extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *move
                               rr_solve_info *info, uint32_t flags, void *workspace, size_t workspace_bytes,
                               void *stream)
 {
-    (void)workspace; (void)workspace_bytes;
     if (!shape_valid(shape) || !flags_valid(flags)) return RR_E_INVAL;
     if (shape.w > RR_MAX_SIDE || shape.h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
     if (!occ || !group_off || !final_occ || !info || (move_cap > 0 && !moves)) return RR_E_INVAL;
@@ -1049,6 +1097,12 @@ extern "C" rr_status rr_solve(rr_shape shape, const uint64_t *occ, rr_move *move
     A.fin = final_occ; A.info = info;
     hipStream_t st = (hipStream_t)stream;
     const uint32_t side = shape.w > shape.h ? shape.w : shape.h;
+    if (side > RR_LDS_SIDE) {
+        if (((flags >> 8) & 0xFu) != 0u) return RR_E_INVAL;    // the wide kernel runs 16 wavefronts
+        if (!workspace || workspace_bytes < kWideBytes || ((uintptr_t)workspace & 255u) != 0) return RR_E_NOMEM;
+        hipLaunchKernelGGL(k_solve_wide_one, dim3(1), dim3(kWideThreads), 0, st, A, (uint8_t *)workspace);
+        return hipGetLastError() == hipSuccess ? RR_OK : RR_E_DEVICE;
+    }
     const uint32_t T = threads_of(flags);
     bool ok;
 #define RR_LAUNCH_ONE(SS, TT) hipLaunchKernelGGL((k_solve_one<SS, TT>), dim3(1), dim3(TT), 0, st, A)
@@ -1063,7 +1117,6 @@ extern "C" rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max
                                    uint64_t *final_arena, rr_solve_info *infos, uint32_t flags, void *workspace,
                                    size_t workspace_bytes, void *stream)
 {
-    (void)workspace; (void)workspace_bytes;
     if (n == 0) return RR_OK;
     if (!flags_valid(flags)) return RR_E_INVAL;
     if (!desc || !occ_arena || !group_arena || !final_arena || !infos || !move_arena) return RR_E_INVAL;
@@ -1071,7 +1124,16 @@ extern "C" rr_status rr_solve_many(uint32_t n, const rr_desc *desc, uint32_t max
     if (max_w > RR_MAX_SIDE || max_h > RR_MAX_SIDE) return RR_E_UNSUPPORTED;
     if (((uintptr_t)move_arena & 7u) != 0) return RR_E_INVAL;
     hipStream_t st = (hipStream_t)stream;
-    const uint32_t side = max_w > max_h ? max_w : max_h;
+    const uint32_t max_side = max_w > max_h ? max_w : max_h;
+    if (max_side > RR_LDS_SIDE) {
+        // instances beyond RR_LDS_SIDE run in the wide kernel, the others in the LDS kernel of
+        // the 256 class; each kernel skips the other's instances
+        if (!workspace || workspace_bytes / kWideBytes < n || ((uintptr_t)workspace & 255u) != 0) return RR_E_NOMEM;
+        hipLaunchKernelGGL(k_solve_wide_many, dim3(n), dim3(kWideThreads), 0, st, desc, (int)max_w, (int)max_h,
+                           occ_arena, move_arena, group_arena, final_arena, infos, flags, (uint8_t *)workspace);
+        if (hipGetLastError() != hipSuccess) return RR_E_DEVICE;
+    }
+    const uint32_t side = max_side > RR_LDS_SIDE ? RR_LDS_SIDE : max_side;
     const uint32_t T = threads_of(flags);
     bool ok;
 #define RR_LAUNCH_MANY(SS, TT)                                                                              \

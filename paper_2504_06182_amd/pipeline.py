@@ -9,7 +9,8 @@ import numpy as np
 import torch
 
 from . import (rr_batch_moves, rr_batch_moves_many, rr_batch_moves_many_staged, rr_batch_workspace_bytes,
-               rr_plan_many, rr_solve, rr_solve_chains, rr_solve_chains_workspace_bytes, rr_solve_many)
+               rr_plan_many, rr_solve, rr_solve_chains, rr_solve_chains_workspace_bytes, rr_solve_many,
+               rr_solve_workspace_bytes)
 from .tune import flags_for, solve_flags_for
 
 SOLVE_INFO_WORDS = 6   # rr_solve_info: int32 status + 5 x uint32
@@ -67,6 +68,8 @@ class SolveBuffers:
         self.group_off = _dev(self.group_cap + 1, torch.int32, device)
         self.final = _dev(self.nwords, torch.int64, device)
         self.info = _dev(SOLVE_INFO_WORDS, torch.int32, device)
+        self.ws_bytes = rr_solve_workspace_bytes(self.shape)     # grids beyond 256 per side
+        self.ws = _dev((self.ws_bytes + 7) // 8, torch.int64, device) if self.ws_bytes else None
 
     def load(self, occ_rows: np.ndarray):
         self.occ.copy_(_u64_to_dev(occ_rows, self.occ.device))
@@ -74,7 +77,7 @@ class SolveBuffers:
 
     def run(self, stream=None):
         rr_solve(self.shape, self.occ, self.moves, self.move_cap, self.group_off, self.group_cap,
-                 self.final, self.info, self.flags, None, 0, stream)
+                 self.final, self.info, self.flags, self.ws, self.ws_bytes, stream)
         return self
 
     def host(self):
@@ -166,6 +169,9 @@ class ManyBuffers:
         self.desc = torch.from_numpy(d.view(np.uint8).copy()).to(device)
         self.steps = self.batches = self.ws = None
         self.ws_bytes = 0
+        big = [s for s in self.shapes if max(s[0], s[1]) > 256]
+        self.solve_ws_bytes = self.n * rr_solve_workspace_bytes(big[0]) if big else 0
+        self.solve_ws = _dev((self.solve_ws_bytes + 7) // 8, torch.int64, device) if big else None
 
     def load(self, grids):
         """grids: list of packed bit-row arrays, one per shot, in order."""
@@ -176,7 +182,7 @@ class ManyBuffers:
 
     def solve(self, stream=None):
         rr_solve_many(self.n, self.desc, self.max_w, self.max_h, self.occ, self.moves, self.groups, self.final,
-                      self.sinfo, self.solve_flags, None, 0, stream)
+                      self.sinfo, self.solve_flags, self.solve_ws, self.solve_ws_bytes, stream)
         return self
 
     def solve_infos(self) -> np.ndarray:

@@ -449,3 +449,60 @@ def graph_tiled(shape, moves, goff, tile_bytes, reduce=True):
                     gbits.setdefault(g, set()).add(grp[a])
     assert not ovf
     return [set(p) for p in preds], gbits, R
+
+
+def wide_graph(shape, moves, goff):
+    """The wide path's graph build (rr_batch_wide.hip, graph): groups in order; a move's in-group
+    predecessors are the earlier moves of its group whose paths meet its own, scanned from the
+    nearest down and skipped when they meet a member already kept (at most 8); a group's
+    predecessor groups are the last groups to touch each of its traps before it (a per-trap
+    word, stamped by each group after it has read).  Returns the graph in the form loop() takes
+    (release codes, successor lists, group lists, heads)."""
+    W, H = shape[0], shape[1]
+    mvs = [tuple(int(v) for v in m) for m in moves]
+    K = len(mvs); G = len(goff) - 1
+    lastg = [None] * (W * H)
+    preds = [[] for _ in range(K)]
+    gpred = [set() for _ in range(G)]
+
+    def traps(m):
+        sx, sy, dx, dy = m
+        st = 1 if dx >= sx else -1
+        out = [sy * W + x for x in range(sx, dx + st, st)]
+        st = 1 if dy >= sy else -1
+        return out + [y * W + dx for y in range(sy + st, dy + st, st)]
+
+    goff = [int(v) for v in goff]
+    for h in range(G):
+        lo, hi = goff[h], goff[h + 1]
+        for b in range(lo, hi):
+            ps = []
+            for a in range(b - 1, lo - 1, -1):
+                if not paths_meet(mvs[a], mvs[b]): continue
+                if any(paths_meet(mvs[u], mvs[a]) for u in ps): continue
+                assert len(ps) < 8, "in-group predecessor set overflow"
+                ps.append(a)
+            preds[b] = ps
+        for b in range(lo, hi):
+            for c in traps(mvs[b]):
+                if lastg[c] is not None: gpred[h].add(lastg[c])
+        for b in range(lo, hi):
+            for c in traps(mvs[b]): lastg[c] = h
+    pend = [len(p) for p in preds]
+    succ = [[] for _ in range(K)]
+    for b in range(K):
+        for a in preds[b]: succ[a].append(b)
+    nx = []; extra = 0
+    for a in range(K):
+        ns = len(succ[a]); code = 0
+        if ns == 1:
+            n = succ[a][0]
+            code = ((1 << 14) | (n - a)) if (pend[n] == 1 and n - a <= 16383) else (2 << 14)
+        elif ns > 1:
+            code = 2 << 14; extra += ns - 1
+        nx.append(code)
+    heads = [[b for b in range(goff[g], goff[g + 1]) if pend[b] == 0] for g in range(G)]
+    gw = [sorted(h for h in range(G) if g in gpred[h]) for g in range(G)]
+    mv = [m[0] | (m[1] << 8) | (m[2] << 16) | (m[3] << 24) for m in mvs]
+    return dict(K=K, G=G, mv=mv, nx=nx, succ=succ, pend=pend, gw=gw, gpend=[len(x) for x in gpred], heads=heads,
+                bound=sum(len(x) for x in heads) + extra, goff=list(goff), preds=preds)

@@ -63,8 +63,32 @@ def test_unknown_solve_order_is_rejected():
 
 
 def test_oversized_grid_is_unsupported():
-    rc = rr.rr_solve((300, 300, 10, 10, 20, 20), 8, 8, 10, 8, 10, 8, 8, 0, None, 0, stream=0, check=False)
+    rc = rr.rr_solve((1100, 300, 10, 10, 20, 20), 8, 8, 10, 8, 10, 8, 8, 0, None, 0, stream=0, check=False)
     assert rc == rr.RR_E_UNSUPPORTED
+    rc = rr.rr_batch_moves((300, 1025, 1, 1, 2, 2), 8, 8, 8, 2, 0, 8, 8, 8, 8, 8, 8, 1 << 20, stream=0, check=False)
+    assert rc == rr.RR_E_UNSUPPORTED
+    rc = rr.rr_solve_many(1, 8, 1025, 32, 8, 8, 8, 8, 8, 0, None, 0, stream=0, check=False)
+    assert rc == rr.RR_E_UNSUPPORTED
+
+
+def test_wide_grids_need_a_solve_workspace():
+    """Grids beyond RR_LDS_SIDE keep the solve's state in the caller's workspace: its size is
+    reported, a missing, short or misaligned one is refused, and so is a wavefront field (the
+    wide kernel runs 16 wavefronts); up to RR_LDS_SIDE none is needed."""
+    assert rr.RR_MAX_SIDE == 1024 and rr.RR_LDS_SIDE == 256
+    assert rr.rr_solve_workspace_bytes((256, 256, 10, 10, 200, 200)) == 0
+    need = rr.rr_solve_workspace_bytes((257, 8, 10, 1, 200, 5))
+    assert need > 0 and need % 256 == 0 and need == rr.rr_solve_workspace_bytes((1024, 1024, 0, 0, 1024, 1024))
+    shape = (300, 300, 10, 10, 290, 290)
+    assert rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, 0, None, 0, stream=0, check=False) == rr.RR_E_NOMEM
+    assert rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, 0, 256, need - 1, stream=0, check=False) == rr.RR_E_NOMEM
+    assert rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, 0, 264, need, stream=0, check=False) == rr.RR_E_NOMEM
+    assert rr.rr_solve(shape, 8, 8, 10, 8, 10, 8, 8, 4 << 8, 256, need, stream=0, check=False) == rr.RR_E_INVAL
+    assert rr.rr_solve_many(3, 8, 300, 300, 8, 8, 8, 8, 8, 0, 256, 3 * need - 1, stream=0,
+                            check=False) == rr.RR_E_NOMEM
+    # batching: the wide layout depends on the grid and the move capacity only
+    a = rr.rr_batch_workspace_bytes(shape, 1000, 10)
+    assert a == rr.rr_batch_workspace_bytes(shape, 1000, 10_000) and a < rr.rr_batch_workspace_bytes(shape, 2000, 10)
 
 
 def test_null_outputs_and_small_workspace_rejected():

@@ -174,3 +174,27 @@ def test_reduced_sets_keep_bird_within_register_sets():
         for ps in red:
             assert not any(M.paths_meet(mv[a], mv[b]) for a in ps for b in ps if a < b)
     assert most_full > 8
+
+
+@pytest.mark.parametrize("algo", ["redrec", "bird"])
+def test_wide_graph_gives_the_oracle_batches(algo):
+    """The wide path's graph build (in-group sets from path meetings, group edges from a per-trap
+    last-group sweep) drives the loop model to the oracle's batches under every constraint, on
+    64 x 64 shots and on uneven shots up to 96 per side; its readiness (in-group ancestors)
+    equals that of the per-trap previous-toucher sets."""
+    shots = ri.config_shots("batch64", n=2) + [d for d in ri.config_shots("mixed", n=12) if d["w"] <= 96][:3]
+    for d in shots:
+        shape = (d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"])
+        r = oracle.solve(shape, ri.shot_grid(d), bird=(algo == "bird"))
+        if r["status"] != 0 or len(r["moves"]) == 0:
+            continue
+        g = M.wide_graph(shape, r["moves"], r["group_off"])
+        full = preds_of(M.graph(shape, r["moves"], r["group_off"], reduce=False))
+        assert ancestors([set(p) for p in g["preds"]]) == ancestors(full)
+        S = 8
+        assert g["bound"] <= 64 * S
+        for flags in (0, 1, 2):
+            b = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=flags)
+            pb, ps, _ = M.loop(g, S, flags)
+            assert np.array_equal(pb, b["batch_off"]), (algo, d["shot"], flags)
+            assert np.array_equal(ps, b["steps"]), (algo, d["shot"], flags)
