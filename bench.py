@@ -29,6 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The served form runs one stream per size-class wave in flight; streams sharing a hardware queue
+# run in submission order, so give HIP (read once, when it starts) a queue per pooled stream: at
+# least 32 (HIP's default is 4).
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 32:
+    os.environ["GPU_MAX_HW_QUEUES"] = "32"
+
 METRIC = "red-rec shots/s batched vs 1-per-launch at 1 GPU; p50/p99 µs per shot (bit-exact)"
 WORKLOAD = "batch64"
 HBM_PEAK_GBS = 8000.0
@@ -443,10 +449,62 @@ def chain_form(args, dev, refs):
                               "hardware": "AMD Threadripper 2950X (CPU); the paper's GPU form stops at 1024 traps"}}
 
 
+def large_form(args, dev):
+    """The served stream's large class alone: 1024 x 1024 shots (p 0.6, centred 780 x 780
+    target) on the wide kernels -- one shot solved and batched a launch at a time (HIP events
+    around each call), then --large-shots shots in one many-instance launch each for solve and
+    batching."""
+    import gc
+
+    import numpy as np
+    import torch
+
+    import rr_inputs as ri
+    from paper_2504_06182_amd.pipeline import BatchBuffers, ManyBuffers, SolveBuffers
+    shots = ri.config_shots("big1024", n=args.large_shots)
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    sb = SolveBuffers(shapes[0], device=dev).load(grids[0])
+    solve_ms = [timed(lambda: sb.run()) for _ in range(3)]
+    h = sb.host()
+    bb = BatchBuffers(sb, step_cap=max(h["n_steps"], 1), device=dev)
+    batch_ms = timed(lambda: bb.run(args.flags))
+    hb = bb.host()
+    out = {"single": {"solve_ms": round(float(np.median(solve_ms)), 2), "batch_ms": round(batch_ms, 1),
+                      "solve_status": h["status"], "batch_status": hb["status"], "moves": h["n_moves"],
+                      "steps": h["n_steps"], "batches": hb.get("n_batches")}}
+    del sb, bb
+    mb = ManyBuffers(shapes, device=dev).load(grids)
+    t_solve = timed(lambda: mb.solve())
+    sinf = mb.solve_infos()
+    mb.plan_batches([max(int(x[3]), 1) for x in sinf])
+    t_batch = timed(lambda: mb.batch(flags=args.flags))
+    binf = mb.batch_infos()
+    out["many"] = {"shots": len(shots), "solve_ms": round(t_solve, 2), "batch_ms": round(t_batch, 1),
+                   "shots_per_s": round(len(shots) / ((t_solve + t_batch) / 1e3), 2),
+                   "all_ok": bool(np.all(sinf[:, 0] == 0) and np.all(binf[:, 0] == 0))}
+    out["workload"] = ("1024 x 1024 grid, i.i.d. Bernoulli(0.6) loading, centred 780 x 780 target; "
+                       f"batching constraint flags {args.flags}")
+    del mb
+    gc.collect()
+    torch.cuda.empty_cache()
+    return out
+
+
 def served_form(args, dev, rate):
     """Served stream: Poisson arrivals at ``rate`` shots/s for --serve-seconds of the uneven
-    mix (grid side uniform over {32..256}), fed to the continuous-batching server; per-shot
-    latency = completion seen by the host - arrival."""
+    mix (grid side uniform over {32..256}) plus, with probability 1/--serve-big-every per
+    arrival, a 1024 x 1024 shot (p 0.6, 780 x 780 target), fed to the continuous-batching
+    server; per-shot latency = completion seen by the host - arrival."""
     import gc
 
     import numpy as np
@@ -455,18 +513,28 @@ def served_form(args, dev, rate):
     import rr_inputs as ri
     from paper_2504_06182_amd.serve import Server, poisson_arrivals, serve_stream
     pool = ri.config_shots("mixed", n=args.serve_pool)
-    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in pool]
-    grids = [ri.shot_grid(d) for d in pool]
+    big = ri.config_shots("big1024", n=4) if args.serve_big_every > 0 else []
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in pool + big]
+    grids = [ri.shot_grid(d) for d in pool + big]
     arrivals = poisson_arrivals(rate, args.serve_seconds, seed=50)
     order = np.arange(len(arrivals)) % len(pool)
-    srv = Server(budget_bytes=args.serve_budget_gib << 30, max_wave=args.serve_max_wave, flags=args.flags)
-    warm = Server(budget_bytes=2 << 30, class_share={64: 0.2, 128: 0.3, 256: 0.5}, flags=args.flags)
-    for j in range(16):                              # first-launch costs outside the measurement
+    if big:
+        pick = np.random.default_rng(51).random(len(arrivals)) < 1.0 / args.serve_big_every
+        order[pick] = len(pool) + np.arange(int(pick.sum())) % len(big)
+    share = {64: 0.04, 128: 0.12, 256: 0.64, 1024: 0.20} if big else None
+    srv = Server(budget_bytes=args.serve_budget_gib << 30, class_share=share, max_wave=args.serve_max_wave,
+                 flags=args.flags)
+    warm = Server(budget_bytes=6 << 30, class_share={64: 0.1, 128: 0.15, 256: 0.35, 1024: 0.4} if big else
+                  {64: 0.2, 128: 0.3, 256: 0.5}, flags=args.flags)
+    for j in list(range(16)) + ([len(pool)] if big else []):   # first-launch costs outside the measurement
         warm.submit(shapes[j], grids[j])
     warm.drain()
     del warm
+    gc.collect()
+    torch.cuda.empty_cache()
     wall = serve_stream(srv, shapes, grids, arrivals, order)
     lat = srv.latencies_us()
+    in_window = sum(1 for sh in srv.shots if sh["t_done"] is not None and sh["t_done"] - srv.t0 <= args.serve_seconds)
     per = {}
     for side in srv.classes:
         l_ = srv.latencies_us(side)
@@ -474,12 +542,17 @@ def served_form(args, dev, rate):
             per[str(side)] = {"n": int(l_.size), "p50_us": round(float(np.percentile(l_, 50)), 1),
                               "p99_us": round(float(np.percentile(l_, 99)), 1)}
     out = {"served_shots_per_s": round(len(arrivals) / wall, 1), "offered_rate": rate,
-            "shots": int(len(arrivals)), "p50_us": round(float(np.percentile(lat, 50)), 1),
+            "completed_in_window_per_s": round(in_window / args.serve_seconds, 1), "wall_s": round(wall, 2),
+            "shots": int(len(arrivals)), "big_shots": int((order >= len(pool)).sum()),
+            "p50_us": round(float(np.percentile(lat, 50)), 1),
             "p99_us": round(float(np.percentile(lat, 99)), 1), "per_class": per, "waves": srv.waves,
             "rerun_alone": srv.overflow, "slots": {str(k): v for k, v in srv.slots().items()},
             "workload": f"Poisson arrivals at {rate:g}/s for {args.serve_seconds:g} s, shots cycling "
-                        f"through {len(pool)} shots of the uneven mix; continuous batching, "
-                        f"{args.serve_budget_gib} GiB of slot arenas, streams per class {srv.STREAMS}"}
+                        f"through {len(pool)} shots of the uneven mix"
+                        + (f", a 1024 x 1024 shot (p 0.6, 780 x 780 target) with probability "
+                           f"1/{args.serve_big_every} per arrival" if big else "")
+                        + f"; continuous batching, {args.serve_budget_gib} GiB of slot arenas, "
+                          f"streams per class {srv.streams_per_class}"}
     del srv
     gc.collect()                                     # the server's arenas go before the next one
     torch.cuda.empty_cache()
@@ -505,6 +578,10 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="20000,10000",
                     help="offered rates of the served stream, one run each (shots/s, comma separated)")
     ap.add_argument("--serve-pool", type=int, default=1024)
+    ap.add_argument("--large-shots", type=int, default=16,
+                    help="1024 x 1024 shots of the large-class form's many-instance launch (0: skip the form)")
+    ap.add_argument("--serve-big-every", type=int, default=4096,
+                    help="a 1024 x 1024 shot with probability 1/N per arrival of the served stream (0: none)")
     ap.add_argument("--serve-budget-gib", type=int, default=176)
     ap.add_argument("--serve-max-wave", type=int, default=1024)
     ap.add_argument("--single-launches", type=int, default=200,
@@ -646,6 +723,7 @@ def main():
     variants = variants_form(args, dev) if not args.no_variants else None
     paper = paper_geometry_form(args, dev, args.paper_shots, refs.get("paper32")) if args.paper_shots > 0 else None
     mixed = mixed_graph_form(args, dev, args.mixed_replays) if args.mixed_replays > 0 else None
+    large = large_form(args, dev) if args.large_shots > 0 else None
     served = None
     if args.serve_seconds > 0:
         runs = [served_form(args, dev, float(r)) for r in args.serve_rates.split(",") if r.strip()]
@@ -690,7 +768,7 @@ def main():
                   "per_launch_sample": len(lat),
                   "batched_step_latency_us": round(ms_per_step * 1e3, 1),
                   "single_instance": single, "paper_geometry": paper, "mixed_graph": mixed,
-                  "served": served, "variants": variants, "chains": chains},
+                  "served": served, "variants": variants, "chains": chains, "large": large},
         "workload_stats": {"solved": n_ok, "infeasible": n - n_ok,
                            "mean_moves": round(float(n_moves.mean()), 1), "mean_steps": round(float(n_steps.mean()), 1),
                            "mean_batches": round(float(n_batches.mean()), 1),

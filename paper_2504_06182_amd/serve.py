@@ -29,7 +29,8 @@ import time
 import numpy as np
 import torch
 
-from . import RR_E_CAPACITY, RR_OK, rr_batch_moves_many, rr_batch_workspace_bytes, rr_solve_many
+from . import (RR_E_CAPACITY, RR_LDS_SIDE, RR_OK, rr_batch_moves_many, rr_batch_workspace_bytes, rr_solve_many,
+               rr_solve_workspace_bytes)
 from .tune import flags_for, solve_flags_for
 from .pipeline import (BATCH_INFO_WORDS, DESC_DTYPE, SOLVE_INFO_WORDS, BatchBuffers, SolveBuffers,
                        solve_caps, words_per_row)
@@ -61,6 +62,10 @@ class _Class:
         self.steps = torch.empty(n * self.step_cap, dtype=torch.int32, device=device)
         self.batches = torch.empty(n * (self.step_cap + 1), dtype=torch.int32, device=device)
         self.ws = torch.empty((n * self.ws_bytes + 7) // 8, dtype=torch.int64, device=device)
+        # grids beyond RR_LDS_SIDE: the solve's per-instance state, one slice per shot of a wave
+        self.solve_ws_bytes = n * rr_solve_workspace_bytes(full)
+        self.solve_ws = (torch.empty((self.solve_ws_bytes + 7) // 8, dtype=torch.int64, device=device)
+                         if self.solve_ws_bytes else None)
         self.free = collections.deque(range(n))
         self.streams = [torch.cuda.Stream(device=device) for _ in range(n_streams)]
         self.on_stream = [None] * n_streams          # the wave last launched on each stream
@@ -78,7 +83,7 @@ class _Class:
         mc, gc = solve_caps(full)
         sc = step_bound(side) if step_cap is None else int(step_cap)
         return (16 * side * words_per_row(side) + 8 * mc + 4 * (gc + 1) + 8 * sc + 4 +
-                rr_batch_workspace_bytes(full, mc, sc) + 256)
+                rr_batch_workspace_bytes(full, mc, sc) + rr_solve_workspace_bytes(full) + 256)
 
 
 class _Wave:
@@ -95,11 +100,17 @@ class Server:
     the host when its wave retires (for checking; off when only timing).  ``slot_steps``: steps a
     slot holds, per class (default step_bound)."""
 
-    # streams per class: one wave each of the two small classes and two of the large one in
-    # flight, four streams for the GPU's four hardware queues -- more streams than queues put
-    # small waves behind large ones on a shared queue (measured at 20k shots/s: 64-class p99
-    # 303 ms with four streams per class, 60 ms with these)
+    # streams per class: one wave each of the two small classes and two of the 256 class in
+    # flight (one 256 stream makes waves so large that they crowd the small classes off the CUs:
+    # 64-class p99 0.7-1.9 s at 20k shots/s).  Streams that share a hardware queue run in
+    # submission order, so a small class behind a 256 wave (~0.2 s) or a 1024 wave (~3 s) on the
+    # same queue waits for it; HIP maps streams onto GPU_MAX_HW_QUEUES queues (4 by default) in
+    # an order the caller does not control, and torch hands out pooled streams, so a process
+    # serving classes this way should run with as many queues as it has streams (bench.py sets
+    # 32).  With 32 queues, at 20k shots/s: 64-class p50 / p99 7 / 65 ms with the 1024 class,
+    # 7 / 76 ms without.
     STREAMS = {64: 1, 128: 1, 256: 2}
+    STREAMS_LARGE = {64: 1, 128: 1, 256: 2, 1024: 1}
 
     def __init__(self, budget_bytes, class_share=None, max_wave=256, streams_per_class=None, flags=0,
                  keep_results=False, device="cuda", slot_steps=None):
@@ -109,9 +120,11 @@ class Server:
         self.keep = bool(keep_results)
         share = class_share or {64: 0.04, 128: 0.12, 256: 0.84}
         if streams_per_class is None:
-            streams_per_class = {side: self.STREAMS.get(side, 1) for side in share}
+            table = self.STREAMS_LARGE if any(side > RR_LDS_SIDE for side in share) else self.STREAMS
+            streams_per_class = {side: table.get(side, 1) for side in share}
         elif not isinstance(streams_per_class, dict):
             streams_per_class = {side: int(streams_per_class) for side in share}
+        self.streams_per_class = dict(streams_per_class)
         self.classes = {}
         slot_steps = slot_steps or {}
         for side, f in share.items():
@@ -198,7 +211,7 @@ class Server:
             w.sinfo = torch.empty(n * SOLVE_INFO_WORDS, dtype=torch.int32, device=self.device)
             w.binfo = torch.empty(n * BATCH_INFO_WORDS, dtype=torch.int32, device=self.device)
             rr_solve_many(n, desc, c.side, c.side, c.occ, c.moves, c.groups, c.final, w.sinfo,
-                          solve_flags_for(c.side), None, 0, st)
+                          solve_flags_for(c.side), c.solve_ws, c.solve_ws_bytes, st)
             rr_batch_moves_many(n, desc, c.side, c.side, c.moves, c.groups, w.sinfo, flags_for(c.side, self.flags),
                                 c.batches, c.steps,
                                 w.binfo, c.ws, c.ws.numel() * 8, st)
@@ -321,6 +334,7 @@ def serve_stream(server: Server, shapes, grids, arrivals, order):
     all are done.  ``order[k]`` is the index into shapes/grids of the k-th arrival.  Returns the
     wall time from the first arrival to the last completion."""
     t0 = time.perf_counter()
+    server.t0 = t0
     k = 0
     n = len(arrivals)
     while k < n or any(server.waiting.values()) or server.inflight:

@@ -113,3 +113,31 @@ def test_served_overflow_rerun_is_asynchronous_and_exact():
     assert srv.overflow == len(shots)
     for i in range(len(shots)):
         same(srv.result(i), alone(shapes[i], grids[i]), f"overflow {i}")
+
+
+def test_served_large_class_equals_alone():
+    """A server with the 1024 class (the stream's occasional 1024 x 1024 shots): two large shots
+    among small ones, on the large class's own stream and wide kernels, return what their
+    single-instance launches return, and the small shots are unaffected."""
+    import gc
+
+    from paper_2504_06182_amd.serve import Server
+    small = ri.config_shots("mixed", n=12)
+    big = ri.config_shots("big1024", n=2)
+    shots = small[:6] + big[:1] + small[6:] + big[1:]
+    shapes = [(d["w"], d["h"], d["x0"], d["y0"], d["x1"], d["y1"]) for d in shots]
+    grids = [ri.shot_grid(d) for d in shots]
+    say("case served large class", len(shots))
+    srv = Server(budget_bytes=8 << 30, class_share={64: 0.05, 128: 0.1, 256: 0.35, 1024: 0.5}, max_wave=4,
+                 keep_results=True)
+    assert srv.slots()[1024] >= 2 and srv.streams_per_class == {64: 1, 128: 1, 256: 2, 1024: 1}
+    ids = [srv.submit(s, g) for s, g in zip(shapes, grids)]
+    srv.drain(timeout_s=300)
+    for i, s, g in zip(ids, shapes, grids):
+        got = srv.result(i)
+        same(got, alone(s, g), f"large class {i} {s[:2]}")
+        if max(s[0], s[1]) > 256:
+            assert got[0]["status"] == 0 and got[1]["n_batches"] > 1_000_000
+    del srv
+    gc.collect()
+    torch.cuda.empty_cache()
