@@ -12,8 +12,10 @@
 //                     * every trap of every move reads the last group that touched it before
 //                       (a per-trap word in the workspace), giving the group's predecessor
 //                       groups as a bit row; then the group stamps its traps.
-//                   From these: successor lists, the groups waiting on each group, and each
-//                   group's head moves (no in-group predecessor).
+//                   From these: successor lists, the groups waiting on each group, each
+//                   group's head moves (no in-group predecessor), and a release record per
+//                   move (its one successor that waits on nothing else, with that successor's
+//                   packed move, when it has such a single successor).
 //   k_wide_loop_*   one wave64: Alg. 3 with the ready set in LDS, sorted by move index, as
 //                   entries (current step code, end of the current leg, next leg, key).  Each
 //                   trip forms one batch -- the first ready move, and under the line-or-column
@@ -39,7 +41,8 @@ constexpr int kGT = 1024;                  // graph kernel threads per instance
 constexpr int kGWaves = kGT / kWave;
 constexpr uint32_t INV = 0xFFFFFFFFu;
 constexpr uint32_t kRcap = 4096;           // ready entries in LDS
-constexpr uint32_t kNcap = 4096;           // moves made ready in one trip
+constexpr uint32_t kNcap = 2048;           // moves made ready in one trip
+enum { REC_NONE = 0u, REC_DIRECT = 1u, REC_LIST = 2u };   // release record kinds (bits 30..31)
 constexpr uint32_t ST_READY = 0x52454459u; // header state: graph built, the loop runs
 enum { H_STATE = 0, H_T = 1, H_K = 2, H_G = 3 };
 enum { ERR_INTERNAL = 1, ERR_CAPACITY = 2 };
@@ -168,6 +171,7 @@ __device__ void scan_ws(uint32_t *a, uint32_t n, GraphShared &S)
 
 struct Ptrs {
     uint32_t *hdr, *lastg, *gbits, *preds, *pend, *scnt, *sfill, *slist, *gpend, *gcnt, *gfill, *glist, *hoff, *heads;
+    uint4 *rec;
     uint32_t gw;
 };
 
@@ -180,6 +184,7 @@ __device__ __forceinline__ Ptrs ptrs_of(const fast::Inst &I)
     P.pend = W32(L.pend); P.scnt = W32(L.scnt); P.sfill = W32(L.sfill); P.slist = W32(L.slist);
     P.gpend = W32(L.gpend); P.gcnt = W32(L.gcnt); P.gfill = W32(L.gfill); P.glist = W32(L.glist);
     P.hoff = W32(L.hoff); P.heads = W32(L.heads);
+    P.rec = (uint4 *)(I.ws + L.rec);
     P.gw = L.gw;
     return P;
 }
@@ -311,19 +316,31 @@ __device__ void graph(const fast::Inst &I, GraphShared &S)
             int len = iabs(dx - sx) + iabs(dy - sy);
             int s = (int)(q0 - S.inc[i]);
             uint32_t lastpg = INV;
-            for (uint32_t q = q0; q < q1; ++q) {
-                if (s > len) {
-                    ++i;
-                    s = 0;
-                    unpack(S.mv[i], sx, sy, dx, dy);
-                    len = iabs(dx - sx) + iabs(dy - sy);
+            constexpr int kB = 8;                  // traps per round: their loads in flight together
+            for (uint32_t q = q0; q < q1; q += kB) {
+                uint32_t cell[kB], pg[kB];
+#pragma unroll
+                for (int u = 0; u < kB; ++u) {
+                    cell[u] = INV;
+                    if (q + u < q1) {
+                        if (s > len) {
+                            ++i;
+                            s = 0;
+                            unpack(S.mv[i], sx, sy, dx, dy);
+                            len = iabs(dx - sx) + iabs(dy - sy);
+                        }
+                        cell[u] = path_trap(W, sx, sy, dx, dy, s);
+                        ++s;
+                    }
                 }
-                const uint32_t pg = P.lastg[path_trap(W, sx, sy, dx, dy, s)];
-                if (pg != INV && pg != lastpg) {
-                    lastpg = pg;
-                    atomicOr(&S.gb[pg >> 5], 1u << (pg & 31u));
-                }
-                ++s;
+#pragma unroll
+                for (int u = 0; u < kB; ++u) pg[u] = cell[u] != INV ? P.lastg[cell[u]] : INV;
+#pragma unroll
+                for (int u = 0; u < kB; ++u)
+                    if (pg[u] != INV && pg[u] != lastpg) {
+                        lastpg = pg[u];
+                        atomicOr(&S.gb[pg[u] >> 5], 1u << (pg[u] & 31u));
+                    }
             }
         }
         __syncthreads();
@@ -397,6 +414,19 @@ __device__ void graph(const fast::Inst &I, GraphShared &S)
         for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b)
             if (P.pend[b] == 0u) P.heads[o++] = b;
     }
+    // ---- release records (the successor lists are complete: scan_ws ended on a barrier)
+    for (uint32_t a = tid; a < K; a += kGT) {
+        const uint32_t lo = P.scnt[a], ns = P.scnt[a + 1] - lo;
+        uint4 r = make_uint4(REC_NONE << 30, 0u, 0u, 0u);
+        if (ns == 1u && P.pend[P.slist[lo]] == 1u) {
+            const uint32_t s2 = P.slist[lo];
+            const uint64_t m = mv64[s2];
+            r = make_uint4((REC_DIRECT << 30) | s2, 0u, (uint32_t)m, (uint32_t)(m >> 32));
+        } else if (ns > 0u) {
+            r.x = REC_LIST << 30;
+        }
+        P.rec[a] = r;
+    }
     if (tid == 0) { P.hdr[H_T] = (uint32_t)T; P.hdr[H_K] = K; P.hdr[H_G] = G; }
     __syncthreads();
     if (tid == 0) P.hdr[H_STATE] = ST_READY;
@@ -409,6 +439,7 @@ struct LoopLds {
     uint32_t rc[kRcap], re[kRcap], rn[kRcap], rk[kRcap];   // ready entries, ascending key
     uint32_t nk[kNcap];                                     // keys made ready this trip
     uint32_t npos[kNcap];                                   // their places in the merged set
+    uint64_t nmv[kNcap];                                    // their packed moves (0: not known yet)
     uint16_t ml[kRcap];                                     // members of the current batch
     uint32_t gpend[kMaxGroups], grem[kMaxGroups];          // group count-downs
     uint32_t nnew, err;
@@ -451,36 +482,43 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
     return v;
 }
 
-__device__ __forceinline__ void push_ready(LoopLds &S, uint32_t key)
+__device__ __forceinline__ void push_ready(LoopLds &S, uint32_t key, uint64_t mv)
 {
     const uint32_t p = atomicAdd(&S.nnew, 1u);
-    if (p < kNcap) S.nk[p] = key;
+    if (p < kNcap) { S.nk[p] = key; S.nmv[p] = mv; }
     else S.err = ERR_CAPACITY;
 }
 
-// a move ended its path: its successors, and when its group completes the groups waiting on it
+// a move ended its path: its successors (one record read for the usual single successor that
+// waits on nothing else), and when its group completes the groups waiting on it
 __device__ __forceinline__ void release(LoopLds &S, const Ptrs &P, uint32_t key)
 {
     const uint32_t b = key >> 11, g = key & 0x7FFu;
-    for (uint32_t t = P.scnt[b], te = P.scnt[b + 1]; t < te; ++t) {
-        const uint32_t s2 = P.slist[t];
-        if (atomic_sub_wg(&P.pend[s2], 1u) == 1u) push_ready(S, (s2 << 11) | g);
+    const uint4 r = P.rec[b];
+    const uint32_t kind = r.x >> 30;
+    if (kind == REC_DIRECT) {
+        push_ready(S, ((r.x & 0x3FFFFFFFu) << 11) | g, (uint64_t)r.z | ((uint64_t)r.w << 32));
+    } else if (kind == REC_LIST) {
+        for (uint32_t t = P.scnt[b], te = P.scnt[b + 1]; t < te; ++t) {
+            const uint32_t s2 = P.slist[t];
+            if (atomic_sub_wg(&P.pend[s2], 1u) == 1u) push_ready(S, (s2 << 11) | g, 0ull);
+        }
     }
     if (atomicSub(&S.grem[g], 1u) == 1u)
         for (uint32_t w = P.gcnt[g], we = P.gcnt[g + 1]; w < we; ++w) {
             const uint32_t h = P.glist[w];
             if (atomicSub(&S.gpend[h], 1u) == 1u)
-                for (uint32_t u = P.hoff[h], ue = P.hoff[h + 1]; u < ue; ++u) push_ready(S, (P.heads[u] << 11) | h);
+                for (uint32_t u = P.hoff[h], ue = P.hoff[h + 1]; u < ue; ++u) push_ready(S, (P.heads[u] << 11) | h, 0ull);
         }
 }
 
-// sort S.nk[0..nn) ascending (bitonic network over the next power of two)
+// sort S.nk[0..nn) ascending, their moves along (bitonic network over the next power of two)
 __device__ void sort_keys(LoopLds &S, uint32_t nn)
 {
     const uint32_t lane = (uint32_t)lane_id();
     uint32_t P2 = 1;
     while (P2 < nn) P2 <<= 1;
-    for (uint32_t i = nn + lane; i < P2; i += kWave) S.nk[i] = INV;
+    for (uint32_t i = nn + lane; i < P2; i += kWave) { S.nk[i] = INV; S.nmv[i] = 0ull; }
     wave_sync();
     for (uint32_t k = 2; k <= P2; k <<= 1)
         for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -489,7 +527,11 @@ __device__ void sort_keys(LoopLds &S, uint32_t nn)
                 if (l > i) {
                     const uint32_t a = S.nk[i], b = S.nk[l];
                     const bool up = (i & k) == 0u;
-                    if ((a > b) == up) { S.nk[i] = b; S.nk[l] = a; }
+                    if ((a > b) == up) {
+                        const uint64_t ma = S.nmv[i], mb = S.nmv[l];
+                        S.nk[i] = b; S.nk[l] = a;
+                        S.nmv[i] = mb; S.nmv[l] = ma;
+                    }
                 }
             }
             wave_sync();
@@ -531,8 +573,10 @@ __device__ void merge_new(LoopLds &S, const uint64_t *mv64, uint32_t &n, uint32_
     }
     for (uint32_t k = lane; k < nn; k += kWave) {
         const uint32_t key = S.nk[k], p = S.npos[k];
+        uint64_t m = S.nmv[k];
+        if (m == 0ull) m = mv64[key >> 11];              // a valid move is never all zero
         uint32_t c, e, x;
-        entry_of(mv64[key >> 11], c, e, x);
+        entry_of(m, c, e, x);
         S.rc[p] = c; S.re[p] = e; S.rn[p] = x; S.rk[p] = key;
     }
     wave_sync();
@@ -575,7 +619,7 @@ __device__ void loop(const fast::Inst &I, LoopLds &S)
     wave_sync();
     for (uint32_t g = lane; g < G; g += kWave)
         if (S.gpend[g] == 0u)
-            for (uint32_t u = P.hoff[g], ue = P.hoff[g + 1]; u < ue; ++u) push_ready(S, (P.heads[u] << 11) | g);
+            for (uint32_t u = P.hoff[g], ue = P.hoff[g + 1]; u < ue; ++u) push_ready(S, (P.heads[u] << 11) | g, 0ull);
     wave_sync();
     uint32_t n = 0;
     {

@@ -33,8 +33,10 @@ __host__ __device__ inline size_t al256(size_t v) { return (v + 255) & ~(size_t)
 //   scnt   successor list offsets (K + 1), sfill fill counters, slist successor lists
 //   gpend  predecessor groups per group, gcnt / gfill / glist the groups waiting on each group
 //   hoff   head-move list offsets per group (G + 1), heads the head moves
+//   rec    release record of each move (16 B): how it releases its successors -- none, one
+//          successor that waits on nothing else (its index and packed move), or a list
 struct Layout {
-    size_t hdr, lastg, gbits, preds, pend, scnt, sfill, slist, gpend, gcnt, gfill, glist, hoff, heads, total;
+    size_t hdr, lastg, gbits, preds, pend, scnt, sfill, slist, gpend, gcnt, gfill, glist, hoff, heads, rec, total;
     uint32_t gw;
 };
 
@@ -59,6 +61,7 @@ __host__ __device__ inline Layout layout(int W, int H, uint32_t move_cap)
     L.glist = take(4 * G * G);
     L.hoff = take(4 * (G + 1));
     L.heads = take(4 * K);
+    L.rec = take(16 * K);
     L.total = p;
     return L;
 }
