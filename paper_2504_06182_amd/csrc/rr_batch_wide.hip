@@ -440,7 +440,8 @@ struct LoopLds {
     uint32_t nk[kNcap];                                     // keys made ready this trip
     uint32_t npos[kNcap];                                   // their places in the merged set
     uint64_t nmv[kNcap];                                    // their packed moves (0: not known yet)
-    uint16_t ml[kRcap];                                     // members of the current batch
+    uint16_t mlr[kRcap], mlc[kRcap];                        // ready moves on the first one's row /
+                                                            // column stepping its way (index order)
     uint32_t gpend[kMaxGroups], grem[kMaxGroups];          // group count-downs
     uint32_t nnew, err;
 };
@@ -553,7 +554,8 @@ __device__ void merge_new(LoopLds &S, const uint64_t *mv64, uint32_t &n, uint32_
         S.npos[k] = k + lo;
     }
     wave_sync();
-    // survivors move up, highest first (a survivor's place never lies below its index)
+    // survivors move up, highest first (a survivor's place never lies below its index); the
+    // ones below the smallest new key stay, so the walk stops at the first chunk of those
     for (int base = ((int)n - 1) & ~(kWave - 1); base >= 0; base -= kWave) {
         const uint32_t i = (uint32_t)base + lane;
         const bool v = i < n;
@@ -567,9 +569,11 @@ __device__ void merge_new(LoopLds &S, const uint64_t *mv64, uint32_t &n, uint32_
             }
             pos = i + lo;
         }
+        const bool moves = v && pos != i;
         wave_sync();
-        if (v) { S.rc[pos] = c; S.re[pos] = e; S.rn[pos] = x; S.rk[pos] = k; }
+        if (moves) { S.rc[pos] = c; S.re[pos] = e; S.rn[pos] = x; S.rk[pos] = k; }
         wave_sync();
+        if (ballot(v && pos == i) != 0ull) break;      // this chunk holds the first survivor that stays
     }
     for (uint32_t k = lane; k < nn; k += kWave) {
         const uint32_t key = S.nk[k], p = S.npos[k];
@@ -583,12 +587,13 @@ __device__ void merge_new(LoopLds &S, const uint64_t *mv64, uint32_t &n, uint32_
     n += nn;
 }
 
-// drop the entries whose key is INV, keeping the order; returns the count left
-__device__ uint32_t compact(LoopLds &S, uint32_t n)
+// drop the entries whose key is INV, keeping the order; returns the count left.  Entries below
+// `from` are all kept and stay where they are.
+__device__ uint32_t compact(LoopLds &S, uint32_t n, uint32_t from)
 {
     const uint32_t lane = (uint32_t)lane_id();
-    uint32_t ns = 0;
-    for (uint32_t base = 0; base < n; base += kWave) {
+    uint32_t ns = from & ~(uint32_t)(kWave - 1);
+    for (uint32_t base = ns; base < n; base += kWave) {
         const uint32_t i = base + lane;
         const bool keep = i < n && S.rk[i] != INV;
         uint32_t c = 0, e = 0, x = 0, k = 0;
@@ -638,98 +643,140 @@ __device__ void loop(const fast::Inst &I, LoopLds &S)
             if (lane == 0) S.err = ERR_INTERNAL;
             break;
         }
-        // ---- the first ready move and the line of the batch
+        // ---- the first ready move
         const uint32_t lc = S.rc[0];
         const uint32_t d1 = lc >> 30;
         const bool horiz = d1 < 2u;
         const uint32_t delta = delta_of(d1);
         const uint32_t ky = lc & MY, kx = lc & MX;
-        bool found = false, row = horiz;
-        uint32_t skey = INV;
-        if (F == RR_LAMBDA_LINE_OR_COL) {
-            for (uint32_t base = 0; base < n; base += kWave) {
-                const uint32_t e = base + lane;
-                bool cand = false;
-                if (e > 0u && e < n) {
-                    const uint32_t c = S.rc[e];
-                    cand = (c & MY) == ky || (c & MX) == kx;
-                }
-                const uint64_t m = ballot(cand);
-                if (m) {
-                    const uint32_t f = base + (uint32_t)__ffsll((unsigned long long)m) - 1u;
-                    row = (S.rc[f] & MY) == ky;
-                    skey = S.rk[f];
-                    found = true;
-                    break;
-                }
-            }
-        } else if (F == RR_LAMBDA_ALONG) {
-            found = true;
-        }
-        const bool along = found && row == horiz;
         const uint32_t p1 = axis_of(lc + delta, horiz);
 
-        // ---- the batch: members step in index order; the convoy bound on the side
-        uint32_t na = 0, tv = INV;
+        // ---- one pass over the ready set: the moves stepping its way on its row and on its
+        //      column (both lists start with it), the first of them after it (which fixes the
+        //      line), and for the convoy the nearest waiting move the sweeping line would reach,
+        //      for each choice of line
+        uint32_t m = 0;                       // members of the batch
+        const uint16_t *ml = S.mlr;           // their places, in index order (unused for NONE)
+        uint32_t tv = INV;                    // convoy bound from waiting moves
+        if (F == RR_LAMBDA_NONE) {
+            m = n;
+        } else if (F == RR_LAMBDA_ALONG) {
+            const uint32_t M = horiz ? MY : MX, kk = horiz ? ky : kx;
+            for (uint32_t base = 0; base < n; base += kWave) {
+                const uint32_t e = base + lane;
+                const bool acc = e < n && (S.rc[e] & M) == kk;
+                const uint64_t b = ballot(acc);
+                if (acc) S.mlr[m + (uint32_t)popc(b & low_mask((int)lane))] = (uint16_t)e;
+                m += (uint32_t)popc(b);
+            }
+        } else {
+            uint32_t mr = 0, mc = 0, fl = kWave;
+            bool found = false, row = horiz;
+            uint32_t tA = INV, tR = INV, tC = INV;
+            for (uint32_t base = 0; base < n; base += kWave) {
+                const uint32_t e = base + lane;
+                const bool valid = e < n;
+                const uint32_t c = valid ? S.rc[e] : 0u;
+                const bool rm = valid && (c & MY) == ky, cm = valid && (c & MX) == kx;
+                const uint64_t br = ballot(rm), bc = ballot(cm);
+                if (rm) S.mlr[mr + (uint32_t)popc(br & low_mask((int)lane))] = (uint16_t)e;
+                if (cm) S.mlc[mc + (uint32_t)popc(bc & low_mask((int)lane))] = (uint16_t)e;
+                mr += (uint32_t)popc(br);
+                mc += (uint32_t)popc(bc);
+                const bool before = !found;   // this chunk's lanes ahead of the first compatible
+                fl = kWave;
+                const uint64_t comp = (br | bc) & (base == 0u ? ~1ull : ~0ull);
+                if (!found && comp) {
+                    fl = (uint32_t)__ffsll((unsigned long long)comp) - 1u;
+                    found = true;
+                    row = ((br >> fl) & 1ull) != 0ull;
+                }
+                if (valid && e > 0u && (c >> 30) == d1) {
+                    const uint32_t p = axis_of(c, horiz);
+                    const uint32_t t = (d1 & 1u) ? p1 - p : p - p1;
+                    if (before && lane < fl) tA = t < tA ? t : tA;
+                    if (!rm) tR = t < tR ? t : tR;
+                    if (!cm) tC = t < tC ? t : tC;
+                }
+            }
+            // a waiting move that the sweeping line reaches in t steps would change the batch:
+            // along the motion, only those ahead of the first compatible one in index order
+            if (!found) {
+                m = 1;                        // the first move alone (mlr[0] is it)
+                tv = wave_min_u32(tR);
+            } else {
+                const bool along = row == horiz;
+                ml = row ? S.mlr : S.mlc;
+                m = row ? mr : mc;
+                tv = wave_min_u32(along ? tA : (row ? tR : tC));
+            }
+        }
+        wave_sync();
+
+        // ---- the batch: members step in index order; for up to 64 members, member r's state
+        //      stays in lane r for the convoy
         bool arrived = false;
-        for (uint32_t base = 0; base < n; base += kWave) {
-            const uint32_t e = base + lane;
-            const bool valid = e < n;
-            const uint32_t c = valid ? S.rc[e] : 0u;
-            bool acc;
-            if (F == RR_LAMBDA_NONE) acc = valid;
-            else acc = valid && (e == 0u || (found && (row ? (c & MY) == ky : (c & MX) == kx)));
-            const uint64_t m = ballot(acc);
-            if (acc) {
-                const uint32_t rank = na + (uint32_t)popc(m & low_mask((int)lane));
-                if (out + rank < I.step_cap) I.steps[out + rank] = c;
-                S.ml[rank] = (uint16_t)e;
+        uint32_t tm = INV, my_c = 0, my_dl = 0, my_e = 0;
+        for (uint32_t r0 = 0; r0 < m; r0 += kWave) {
+            const uint32_t r = r0 + lane;
+            if (r < m) {
+                const uint32_t e = F == RR_LAMBDA_NONE ? r : (uint32_t)ml[r];
+                const uint32_t c = S.rc[e];
+                if (out + r < I.step_cap) I.steps[out + r] = c;
                 const uint32_t dl = F == RR_LAMBDA_NONE ? delta_of(c >> 30) : delta;
                 const uint32_t c2 = c + dl, ee = S.re[e];
                 S.rc[e] = c2;
                 const bool h = (c2 >> 30) < 2u;
                 const uint32_t a1 = axis_of(ee, h), a2 = axis_of(c2, h);
                 const uint32_t rem = a1 > a2 ? a1 - a2 : a2 - a1;
-                tv = rem < tv ? rem : tv;
+                tm = rem < tm ? rem : tm;
                 arrived |= c2 == ee;
-            } else if (F == RR_LAMBDA_LINE_OR_COL && valid && (c >> 30) == d1 && !(along && S.rk[e] > skey)) {
-                // a waiting move the sweeping line reaches in t steps would change the batch
-                const uint32_t p = axis_of(c, horiz);
-                const uint32_t t = (d1 & 1u) ? p1 - p : p - p1;
-                tv = t < tv ? t : tv;
+                if (r0 == 0u) { my_c = c2; my_dl = dl; my_e = e; }
             }
-            na += (uint32_t)popc(m);
         }
         bool any = ballot(arrived) != 0ull;
+        const uint32_t na = m;
         out += na;
         ++nb;
         if (lane == 0 && nb <= I.batch_cap) I.boff[nb] = out;
 
         // ---- the convoy: the same batch ts more times
         if (!any) {
-            const uint32_t ts = wave_min_u32(tv);
+            const uint32_t tmin = wave_min_u32(tm);
+            const uint32_t ts = tmin < tv ? tmin : tv;
             if (ts > 0u) {
                 if ((uint64_t)nb + ts > T || (uint64_t)out + (uint64_t)ts * na > T) {
                     if (lane == 0) S.err = ERR_INTERNAL;
                     break;
                 }
-                wave_sync();
                 const uint32_t total = ts * na, dj = (uint32_t)kWave / na, dr = (uint32_t)kWave % na;
                 uint32_t j = lane / na, r = lane % na;
-                for (uint32_t q = lane; q < total; q += kWave) {
-                    const uint32_t c = S.rc[S.ml[r]];
-                    const uint32_t dl = F == RR_LAMBDA_NONE ? delta_of(c >> 30) : delta;
-                    if (out + q < I.step_cap) I.steps[out + q] = c + j * dl;
-                    j += dj;
-                    r += dr;
-                    if (r >= na) { r -= na; ++j; }
+                if (na <= (uint32_t)kWave) {
+                    for (uint32_t q0 = 0; q0 < total; q0 += kWave) {
+                        const uint32_t c = (uint32_t)__shfl((int)my_c, (int)r, kWave);
+                        const uint32_t dl = (uint32_t)__shfl((int)my_dl, (int)r, kWave);
+                        const uint32_t q = q0 + lane;
+                        if (q < total && out + q < I.step_cap) I.steps[out + q] = c + j * dl;
+                        j += dj;
+                        r += dr;
+                        if (r >= na) { r -= na; ++j; }
+                    }
+                } else {
+                    for (uint32_t q = lane; q < total; q += kWave) {
+                        const uint32_t c = S.rc[F == RR_LAMBDA_NONE ? r : (uint32_t)ml[r]];
+                        const uint32_t dl = F == RR_LAMBDA_NONE ? delta_of(c >> 30) : delta;
+                        if (out + q < I.step_cap) I.steps[out + q] = c + j * dl;
+                        j += dj;
+                        r += dr;
+                        if (r >= na) { r -= na; ++j; }
+                    }
                 }
                 for (uint32_t jj = lane; jj < ts; jj += kWave)
                     if (nb + jj + 1u <= I.batch_cap) I.boff[nb + jj + 1u] = out + (jj + 1u) * na;
                 wave_sync();
                 bool arr = false;
                 for (uint32_t rr = lane; rr < na; rr += kWave) {
-                    const uint32_t e = S.ml[rr];
+                    const uint32_t e = F == RR_LAMBDA_NONE ? rr : (uint32_t)ml[rr];
                     const uint32_t c = S.rc[e];
                     const uint32_t dl = F == RR_LAMBDA_NONE ? delta_of(c >> 30) : delta;
                     const uint32_t c2 = c + ts * dl;
@@ -742,16 +789,17 @@ __device__ void loop(const fast::Inst &I, LoopLds &S)
                 wave_sync();
             }
         }
+        (void)my_e;
         if (!any) continue;
 
         // ---- legs ended: turn, or finish and release
-        uint32_t ndone = 0;
+        uint32_t ndone = 0, first_done = INV;
         for (uint32_t r0 = 0; r0 < na; r0 += kWave) {
             const uint32_t rr = r0 + lane;
             bool done = false;
             uint32_t key = 0;
             if (rr < na) {
-                const uint32_t e = S.ml[rr];
+                const uint32_t e = F == RR_LAMBDA_NONE ? rr : (uint32_t)ml[rr];
                 const uint32_t c = S.rc[e];
                 if (c == S.re[e]) {
                     const uint32_t nx = S.rn[e];
@@ -763,16 +811,18 @@ __device__ void loop(const fast::Inst &I, LoopLds &S)
                         done = true;
                         key = S.rk[e];
                         S.rk[e] = INV;
+                        first_done = e < first_done ? e : first_done;
                     }
                 }
             }
             if (done) release(S, P, key);
             ndone += (uint32_t)popc(ballot(done));
         }
+        first_done = wave_min_u32(first_done);
         wave_sync();
         if (ndone == 0u) continue;
         alive -= ndone;
-        n = compact(S, n);
+        n = compact(S, n, first_done);
         const uint32_t nn = S.nnew;
         if (S.err != 0u) break;
         if (n + nn > kRcap) {
