@@ -262,19 +262,29 @@ __device__ __forceinline__ bool paths_meet(uint32_t p, uint32_t q)
     return hh || hv || vh || vv;
 }
 
-// Add in-group predecessor v (packed coordinates vc) to the set s[0..n) of one move (packed
-// coordinates in pc), keeping the set free of redundant members: two moves of one group whose
-// paths meet are joined by an edge of the dependency graph (the earlier precedes the later), so
-// of two members whose paths meet the earlier is an ancestor of the later and adds nothing to
-// the move's readiness.  Such earlier members are dropped (v too, when a later member meets it);
-// readiness, hence every batch, is unchanged.  Sets ovf when a needed member does not fit.
-__device__ __forceinline__ void pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc)[kMaxPreds], int &n, uint32_t v,
-                                         uint32_t vc, bool &ovf)
+// Add in-group predecessor v to the set s[0..n) of one move, keeping the set free of redundant
+// members: two moves of one group whose paths meet are joined by an edge of the dependency
+// graph (the earlier precedes the later), so of two members whose paths meet the earlier is an
+// ancestor of the later and adds nothing to the move's readiness.  Such earlier members are
+// dropped (v too, when a later member meets it); readiness, hence every batch, is unchanged.
+// Sets ovf when a needed member does not fit.  pc[] holds the members' packed coordinates, 0
+// while not read yet (a move is never all zero): they are read only once a set has a member,
+// so the usual sets of zero or one (red-rec's) cost no extra reads.  Returns whether the set
+// changed.
+__device__ __forceinline__ bool pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc)[kMaxPreds], int &n, uint32_t v,
+                                         const rr_move *mv, bool &ovf)
 {
     bool have = false;
 #pragma unroll
     for (int i = 0; i < kMaxPreds; ++i) have |= (i < n) && s[i] == v;
-    if (have) return;
+    if (have) return false;
+    if (n == 0) {
+        s[0] = v;
+        pc[0] = 0u;
+        n = 1;
+        return true;
+    }
+    const uint32_t vc = packed_move(mv, v);
     bool redundant = false;
     uint32_t ks[kMaxPreds], kc[kMaxPreds];
     int m = 0;
@@ -282,6 +292,7 @@ __device__ __forceinline__ void pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc
     for (int i = 0; i < kMaxPreds; ++i) {
         ks[i] = 0; kc[i] = 0;
         if (i >= n) continue;
+        if (pc[i] == 0u) pc[i] = packed_move(mv, s[i]);
         const bool meet = paths_meet(pc[i], vc);
         redundant |= meet && s[i] > v;
         const bool keep = !(meet && s[i] < v);
@@ -291,7 +302,7 @@ __device__ __forceinline__ void pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc
         m += keep ? 1 : 0;
     }
     if (!redundant) {
-        if (m == kMaxPreds) { ovf = true; return; }
+        if (m == kMaxPreds) { ovf = true; return false; }
 #pragma unroll
         for (int j = 0; j < kMaxPreds; ++j)
             if (j == m) { ks[j] = v; kc[j] = vc; }
@@ -300,6 +311,7 @@ __device__ __forceinline__ void pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc
 #pragma unroll
     for (int i = 0; i < kMaxPreds; ++i) { s[i] = ks[i]; pc[i] = kc[i]; }
     n = m;
+    return true;
 }
 
 template <int NT>
@@ -387,7 +399,7 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
             last = a;
             const uint32_t ga = grp[a];
             if (ga == g) {
-                pred_add(ps, pc, np, a, packed_move(I.moves, a), ovf);
+                pred_add(ps, pc, np, a, I.moves, ovf);
             } else if (ga != lastg) {        // a group predecessor: the bit matrix keeps it once
                 lastg = ga;
                 __hip_atomic_fetch_or(&gbits[g * GW + ga / 32], 1u << (ga & 31), __ATOMIC_RELAXED,
@@ -738,11 +750,10 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
                         np = (int)pend[b];
 #pragma unroll
                         for (int i = 0; i < kMaxPreds; ++i)
-                            if (i < np) { ps[i] = preds[(size_t)b * kMaxPreds + i]; pc[i] = packed_move(I.moves, ps[i]); }
+                            if (i < np) { ps[i] = preds[(size_t)b * kMaxPreds + i]; pc[i] = 0u; }
                         loaded = true;
                     }
-                    pred_add(ps, pc, np, a, packed_move(I.moves, a), ovf);
-                    changed = true;
+                    changed |= pred_add(ps, pc, np, a, I.moves, ovf);
                 } else {
                     const uint32_t ga = grp[a];
                     if (ga != lastg) {
@@ -793,11 +804,10 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
                             np = (int)pend[b];
 #pragma unroll
                             for (int i = 0; i < kMaxPreds; ++i)
-                                if (i < np) { ps[i] = preds[(size_t)b * kMaxPreds + i]; pc[i] = packed_move(I.moves, ps[i]); }
+                                if (i < np) { ps[i] = preds[(size_t)b * kMaxPreds + i]; pc[i] = 0u; }
                             loaded = true;
                         }
-                        pred_add(ps, pc, np, u, packed_move(I.moves, u), ovf);
-                        changed = true;
+                        changed |= pred_add(ps, pc, np, u, I.moves, ovf);
                     } else {
                         const uint32_t gu = (uint32_t)__builtin_amdgcn_readlane((int)ga, l);
                         if (gu != lastg) {
