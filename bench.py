@@ -477,11 +477,15 @@ def large_form(args, dev):
     solve_ms = [timed(lambda: sb.run()) for _ in range(3)]
     h = sb.host()
     bb = BatchBuffers(sb, step_cap=max(h["n_steps"], 1), device=dev)
-    batch_ms = timed(lambda: bb.run(args.flags))
-    hb = bb.host()
-    out = {"single": {"solve_ms": round(float(np.median(solve_ms)), 2), "batch_ms": round(batch_ms, 1),
-                      "solve_status": h["status"], "batch_status": hb["status"], "moves": h["n_moves"],
-                      "steps": h["n_steps"], "batches": hb.get("n_batches")}}
+    per_flags = {}
+    for f in [int(v) for v in args.large_flags.split(",")] if args.large_flags else [args.flags]:
+        t = timed(lambda: bb.run(f))
+        hb = bb.host()
+        per_flags[str(f)] = {"batch_ms": round(t, 1), "batch_status": hb["status"], "batches": hb.get("n_batches")}
+    first = next(iter(per_flags.values()))
+    out = {"single": {"solve_ms": round(float(np.median(solve_ms)), 2), "batch_ms": first["batch_ms"],
+                      "solve_status": h["status"], "batch_status": first["batch_status"], "moves": h["n_moves"],
+                      "steps": h["n_steps"], "batches": first["batches"], "per_constraint": per_flags}}
     del sb, bb
     mb = ManyBuffers(shapes, device=dev).load(grids)
     t_solve = timed(lambda: mb.solve())
@@ -580,6 +584,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=1024)
     ap.add_argument("--large-shots", type=int, default=16,
                     help="1024 x 1024 shots of the large-class form's many-instance launch (0: skip the form)")
+    ap.add_argument("--large-flags", type=str, default="",
+                    help="batching constraints (comma separated) of the large-class form's single shot (default --flags)")
     ap.add_argument("--serve-big-every", type=int, default=4096,
                     help="a 1024 x 1024 shot with probability 1/N per arrival of the served stream (0: none)")
     ap.add_argument("--serve-budget-gib", type=int, default=176)
