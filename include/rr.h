@@ -21,8 +21,9 @@
  *    smaller than the matching *_workspace_bytes() (RR_E_NOMEM) or a launch failure
  *    (RR_E_DEVICE).  Outcomes that depend on the data are written to the device-side info
  *    struct: RR_OK, RR_INFEASIBLE (no move, final = input), RR_E_CAPACITY (an output array is too
- *    small; need_* hold the exact sizes, contents of the outputs are unspecified) or RR_E_INVAL
- *    (malformed device-side input, e.g. a move off the grid).
+ *    small; need_* hold the exact sizes, contents of the outputs are unspecified), RR_E_INVAL
+ *    (malformed device-side input, e.g. a move off the grid) or, from the batching path of grids
+ *    beyond RR_LDS_SIDE, RR_E_UNSUPPORTED (an instance beyond that path's fixed capacities).
  *  - Every result is deterministic: the same input gives the same bytes, whatever the launch
  *    configuration, and equals the CPU reference bit for bit.
  *  - Calls on different streams that share no output or workspace memory may run concurrently.
@@ -163,7 +164,13 @@ size_t rr_batch_workspace_bytes(rr_shape shape, uint32_t move_cap, uint32_t step
  *                    (1, 2 or 4: 4, 8 or 16 wavefronts; 0 = the default, 8), another tuning
  *                    knob.  Bits 17..19 must be 0.
  *                    At most 2^20 - 1 moves in at most 1024 groups (always true for rr_solve
- *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.
+ *                    outputs on grids up to 256 x 256); more gives RR_E_INVAL.  Grids beyond
+ *                    RR_LDS_SIDE run the wide path: at most 2^21 - 1 moves, at most W + H (and
+ *                    2048) groups of at most 2048 moves each (RR_E_INVAL beyond), every flag
+ *                    bit but the constraint ignored; an instance whose in-group predecessor
+ *                    sets or ready set outgrow the path's fixed capacities (8 members after
+ *                    pruning; 4096 ready moves, 2048 made ready at once -- rr_solve outputs
+ *                    stay far below) gives RR_E_UNSUPPORTED.
  *   batch_off  [out] uint32_t[batch_cap + 1]: steps of batch k are [batch_off[k], batch_off[k+1]).
  *   steps      [out] uint32_t[step_cap]: dir << 30 | x << 15 | y, the source trap of each unit
  *                    step, dir 0 = +x, 1 = -x, 2 = +y, 3 = -y.  step_cap >= sinfo->n_steps and
