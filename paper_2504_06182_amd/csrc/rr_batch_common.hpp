@@ -62,11 +62,17 @@ extern __shared__ __attribute__((aligned(16))) uint8_t dyn_lds[];
 
 // ---- loop kernels (S register slots, F the local constraint: one kernel per constraint)
 
+// Waves per SIMD the many-instance loop kernel is compiled for: 8 with 3 register slots (a
+// budget of 64 VGPRs and 96 SGPRs per wave; the compiler's own choice used 104 SGPRs, leaving
+// room for 7, so an 8192-instance launch ran a second round on 1024 SIMDs); the larger ready
+// sets keep the compiler's choice (8 would spill them to scratch).
+constexpr int loop_waves(int S) { return S == 3 ? 8 : 1; }
+
 template <int S, uint32_t F>
 __global__ __launch_bounds__(kWave) void k_loop_one(fast::Inst I, uint32_t lds_bytes);
 
 template <int S, uint32_t F>
-__global__ __launch_bounds__(kWave) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
+__global__ __launch_bounds__(kWave, loop_waves(S)) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                      const rr_move *mv, const uint32_t *ga,
                                                      const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
                                                      rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,

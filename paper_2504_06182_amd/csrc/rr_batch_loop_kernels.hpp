@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kWave) void k_loop_one(fast::Inst I, uint32_t lds_b
 }
 
 template <int S, uint32_t F>
-__global__ __launch_bounds__(kWave) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
+__global__ __launch_bounds__(kWave, loop_waves(S)) void k_loop_many(const rr_desc *__restrict__ desc, int maxw, int maxh,
                                                      const rr_move *mv, const uint32_t *ga,
                                                      const rr_solve_info *sinfos, uint32_t *bat, uint32_t *stp,
                                                      rr_batch_info *binfos, uint8_t *ws, uint64_t ws_bytes,
