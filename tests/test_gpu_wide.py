@@ -222,3 +222,25 @@ def test_wide_capacity_and_status():
     rc = rr.rr_solve(shape, s3.occ, s3.moves, s3.move_cap, s3.group_off, s3.group_cap, s3.final, s3.info, 4 << 8,
                      s3.ws, s3.ws_bytes, stream=None, check=False)
     assert rc == rr.RR_E_INVAL
+
+
+def test_wide_degenerate_shapes():
+    """Thin and extreme wide grids: one row or one column of 1024 traps, two rows of 700, 1024 x 3
+    and 3 x 1024 with side-column targets, a full target on a 300 x 300 grid loaded at 0.95, a
+    single-trap target: solve and line-or-column batching equal the oracle (a refused instance
+    batches to nothing)."""
+    cases = [((1024, 1, 100, 0, 900, 1), 0.8), ((1, 1024, 0, 100, 1, 900), 0.8), ((700, 2, 50, 0, 650, 2), 0.9),
+             ((1024, 3, 10, 1, 1000, 2), 0.5), ((3, 1024, 1, 10, 2, 1000), 0.5), ((300, 300, 0, 0, 300, 300), 0.95),
+             ((400, 300, 200, 150, 201, 151), 0.3)]
+    for k, (shape, p) in enumerate(cases):
+        occ = ri.pack_rows(ri.bernoulli_grid(904, k, shape[0], shape[1], p))
+        say("case wide degenerate", shape)
+        r = oracle.solve(shape, occ)
+        sb, g = gpu_solve(shape, occ)
+        same_solve(g, r, f"degenerate {shape}")
+        if r["status"] == 0:
+            rb = oracle.batch(shape, r["moves"], r["group_off"], r["n_steps"], flags=0, indexed=True)
+            same_batch(gpu_batch(sb, r["n_steps"], 0), rb, f"degenerate batch {shape}")
+        else:
+            h = gpu_batch(sb, 0, 0)
+            assert h["status"] == 0 and h["n_batches"] == 0
