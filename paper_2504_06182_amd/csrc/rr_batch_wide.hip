@@ -192,6 +192,7 @@ __device__ __forceinline__ Ptrs ptrs_of(const fast::Inst &I)
 __device__ void graph(const fast::Inst &I, GraphShared &S)
 {
     const uint32_t tid = threadIdx.x;
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
     const int W = I.W, H = I.H;
     const Ptrs P = ptrs_of(I);
     const uint64_t *mv64 = reinterpret_cast<const uint64_t *>(I.moves);
@@ -265,39 +266,69 @@ __device__ void graph(const fast::Inst &I, GraphShared &S)
         }
         __syncthreads();
 
-        // in-group predecessor sets, nearest candidates first
-        for (uint32_t i = tid; i < n; i += kGT) {
+        // in-group predecessor sets, nearest candidates first.  A wave per move (moves dealt
+        // round-robin to the waves), its lanes testing 64 earlier moves at once: the nearest one
+        // whose path meets the move's is kept; of the rest only those whose paths meet the move's
+        // but not the kept one's can be kept too -- a lane-parallel filter -- and those few go in
+        // order, each kept unless its path meets one already kept.  The same sets as a scan from
+        // the nearest down, candidate by candidate.
+        for (uint32_t i = (uint32_t)wid; i < n; i += kGWaves) {
             const uint64_t mb = S.mv[i];
+            int m1 = -1;
+            for (int top = (int)i - 1; top >= 0 && m1 < 0; top -= kWave) {
+                const int a = top - lane;
+                const bool meet = a >= 0 && paths_meet(S.mv[a], mb);
+                const uint64_t mk = ballot(meet);
+                if (mk) m1 = top - (__ffsll((unsigned long long)mk) - 1);   // lowest lane: nearest
+            }
             uint32_t ps[kMaxPreds];
             uint64_t pc[kMaxPreds];
 #pragma unroll
             for (int k = 0; k < kMaxPreds; ++k) { ps[k] = 0u; pc[k] = 0ull; }
             int np = 0;
             bool ovf = false;
-            for (int a = (int)i - 1; a >= 0; --a) {
-                const uint64_t ma = S.mv[a];
-                if (!paths_meet(ma, mb)) continue;
-                bool red = false;
+            if (m1 >= 0) {
+                ps[0] = (uint32_t)m1;
+                pc[0] = S.mv[m1];
+                np = 1;
+                for (int top = m1 - 1; top >= 0 && !ovf; top -= kWave) {
+                    const int a = top - lane;
+                    bool cand = false;
+                    if (a >= 0) {
+                        const uint64_t ma = S.mv[a];
+                        cand = paths_meet(ma, mb) && !paths_meet(ma, pc[0]);
+                    }
+                    uint64_t mk = ballot(cand);
+                    while (mk) {                                   // nearest first
+                        const int l = __ffsll((unsigned long long)mk) - 1;
+                        mk &= mk - 1;
+                        const int ac = top - l;
+                        const uint64_t mac = S.mv[ac];
+                        bool red = false;
 #pragma unroll
-                for (int k = 0; k < kMaxPreds; ++k) red |= k < np && paths_meet(pc[k], ma);
-                if (red) continue;
-                if (np == kMaxPreds) { ovf = true; break; }
+                        for (int k = 1; k < kMaxPreds; ++k)
+                            if (k < np && !red) red = paths_meet(pc[k], mac);
+                        if (red) continue;
+                        if (np == kMaxPreds) { ovf = true; break; }
+#pragma unroll
+                        for (int k = 1; k < kMaxPreds; ++k)
+                            if (k == np) { ps[k] = (uint32_t)ac; pc[k] = mac; }
+                        ++np;
+                    }
+                }
+            }
+            if (lane == 0) {
+                const uint32_t b = lo + i;
+                P.pend[b] = (uint32_t)np;
 #pragma unroll
                 for (int k = 0; k < kMaxPreds; ++k)
-                    if (k == np) { ps[k] = (uint32_t)a; pc[k] = ma; }
-                ++np;
+                    if (k < np) {
+                        P.preds[(size_t)b * kMaxPreds + k] = lo + ps[k];
+                        atomic_add_wg(&P.scnt[lo + ps[k]], 1u);
+                    }
+                if (ovf) S.flags = 1u;
             }
-            const uint32_t b = lo + i;
-            P.pend[b] = (uint32_t)np;
-#pragma unroll
-            for (int k = 0; k < kMaxPreds; ++k)
-                if (k < np) {
-                    P.preds[(size_t)b * kMaxPreds + k] = lo + ps[k];
-                    atomic_add_wg(&P.scnt[lo + ps[k]], 1u);
-                }
-            if (ovf) S.flags = 1u;
         }
-
         // the group's traps: read the previous group of each (contiguous chunks of the traps)
         const uint32_t tot = S.inc[n];
         const uint32_t ch = (tot + kGT - 1) / kGT;
