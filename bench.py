@@ -109,7 +109,7 @@ def oracle_references(verify_shots: int, paper_shots: int, flags: int):
 
 
 BATCH_SOURCES = ("rr_batch.hip", "rr_batch_graph.hpp", "rr_batch_loop.hpp", "rr_batch_generic.hpp", "rr_device.hpp",
-                 "rr_batch_common.hpp", "rr_batch_loop_kernels.hpp", "rr_batch_loop3.hip")
+                 "rr_batch_common.hpp", "rr_batch_loop_kernels.hpp", "rr_batch_loop2.hip")
 PROFILE = os.path.join(ROOT, "profiles", "k_loop_many_batch64.md")
 
 
@@ -128,7 +128,7 @@ def measured_traffic(flags):
         text = open(PROFILE).read()
     except OSError:
         return None
-    m = re.search(r"traffic_bytes_per_launch k_loop_many<3,0> (\d+) sources_sha256 ([0-9a-f]+) flags (\d+)", text)
+    m = re.search(r"traffic_bytes_per_launch k_loop_many<2,0> (\d+) sources_sha256 ([0-9a-f]+) flags (\d+)", text)
     if not m or m.group(2) != sha or int(m.group(3)) != int(flags):
         return None
     return float(m.group(1))
@@ -762,7 +762,7 @@ def main():
                        "batch_generic": round(k_generic, 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic, "kernel": "k_loop_many<3,0>",
+                     "traffic": traffic, "kernel": "k_loop_many<2,0>",
                      "algorithmic_bytes_per_launch": bytes_batch},
         "solve_roofline": {"achieved": round(bytes_solve / (k_solve / 1e3) / 1e9, 2), "unit": "GB/s",
                            "algorithmic_bytes_per_launch": bytes_solve},

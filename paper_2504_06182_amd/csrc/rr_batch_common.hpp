@@ -1,6 +1,6 @@
 // rr_batch_common.hpp -- what the batching translation units share: descriptor checks, the
 // per-instance view of a many-instance launch, and the loop kernels' declarations (their
-// definitions are instantiated in rr_batch_loop3/5/8.hip, one file per register-slot count, so
+// definitions are instantiated in rr_batch_loop2/5/8.hip, one file per register-slot count, so
 // that the three compile in parallel).
 #pragma once
 #include "rr_device.hpp"
@@ -62,11 +62,11 @@ extern __shared__ __attribute__((aligned(16))) uint8_t dyn_lds[];
 
 // ---- loop kernels (S register slots, F the local constraint: one kernel per constraint)
 
-// Waves per SIMD the many-instance loop kernel is compiled for: 8 with 3 register slots (a
-// budget of 64 VGPRs and 96 SGPRs per wave; the compiler's own choice used 104 SGPRs, leaving
-// room for 7, so an 8192-instance launch ran a second round on 1024 SIMDs); the larger ready
-// sets keep the compiler's choice (8 would spill them to scratch).
-constexpr int loop_waves(int S) { return S == 3 ? 8 : 1; }
+// Waves per SIMD the many-instance loop kernel is compiled for: 8 with 2 register slots (its
+// own choice, 106 SGPRs, leaves room for 7, so an 8192-instance launch would run a second round
+// on 1024 SIMDs; the bound of 8 spills uniform values to VGPR lanes and still runs faster); the
+// larger ready sets keep the compiler's choice (8 would spill them to scratch).
+constexpr int loop_waves(int S) { return S == 2 ? 8 : 1; }
 
 template <int S, uint32_t F>
 __global__ __launch_bounds__(kWave) void k_loop_one(fast::Inst I, uint32_t lds_bytes);
