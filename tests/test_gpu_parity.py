@@ -331,7 +331,7 @@ def _load_crafted(sb, mv, goff, n_steps):
 
 def test_ready_set_overflow_hands_over_to_general_path():
     """A ready set that outgrows the loop's registers mid-run (hand-made wide release: 4 ready
-    moves, then 240 at once on a 64 x 64 grid, whose loop holds 192): the instance is redone on
+    moves, then 240 at once on a 64 x 64 grid, whose loop holds 128): the instance is redone on
     the general path, with the oracle's batches, in one-instance and many-instance launches and
     with the loop data in LDS and in the workspace."""
     from crafted import wide_release
