@@ -7,7 +7,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rr_batch_loop8.hip", "rr_batch_loop5.hip", "rr_batch_loop2.hip",
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("rr_batch_loop6.hip", "rr_batch_loop5.hip", "rr_batch_loop2.hip",
                                                    "rr_batch_wide.hip", "rr_batch.hip", "rr_solve.hip",
                                                    "rr_chain.hip")]
 HEADERS = [os.path.join(HERE, "csrc", h) for h in ("rr_device.hpp", "rr_batch_generic.hpp", "rr_batch_graph.hpp",

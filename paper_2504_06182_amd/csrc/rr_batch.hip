@@ -71,11 +71,11 @@ __global__ __launch_bounds__(NT) void k_graph_many(const rr_desc *__restrict__ d
                       (flags & kFlagGeneric) != 0);
 }
 
-// ---- loop kernels: instantiated in rr_batch_loop2/5/8.hip
+// ---- loop kernels: instantiated in rr_batch_loop2/5/6.hip
 
 RR_LOOP_KERNELS(extern, 2)
 RR_LOOP_KERNELS(extern, 5)
-RR_LOOP_KERNELS(extern, 8)
+RR_LOOP_KERNELS(extern, 6)
 
 // ---- general path
 
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_many(uint32_t n, rr_desc 
 // outputs stay near two moves per target row (88 or 89 at most on 64 x 64 grids with a 44 x 44
 // target); 128 positions hold them for 64-trap sides, with registers to spare for 8 waves per
 // SIMD.  An instance whose set outgrows the slots is redone by the general path.
-static int loop_slots(uint32_t max_side) { return max_side <= 64 ? 2 : (max_side <= 128 ? 5 : 8); }
+static int loop_slots(uint32_t max_side) { return max_side <= 64 ? 2 : (max_side <= 128 ? 5 : 6); }
 
 // LDS one workgroup may take on the current device (read once per device, so that later calls,
 // also under stream capture, make no device query)
@@ -323,7 +323,7 @@ extern "C" rr_status rr_batch_moves(rr_shape shape, const rr_move *moves, const 
     switch (P.S) {
     case 2: RR_LOOP_ONE_F(2); break;
     case 5: RR_LOOP_ONE_F(5); break;
-    default: RR_LOOP_ONE_F(8); break;
+    default: RR_LOOP_ONE_F(6); break;
     }
 #undef RR_LOOP_ONE_F
 #undef RR_LOOP_ONE
@@ -379,7 +379,7 @@ extern "C" rr_status rr_batch_moves_many_staged(uint32_t n, const rr_desc *desc,
     switch (P.S) {
     case 2: RR_LOOP_MANY_F(2); break;
     case 5: RR_LOOP_MANY_F(5); break;
-    default: RR_LOOP_MANY_F(8); break;
+    default: RR_LOOP_MANY_F(6); break;
     }
 #undef RR_LOOP_MANY_F
 #undef RR_LOOP_MANY

@@ -1,6 +1,6 @@
 // rr_batch_common.hpp -- what the batching translation units share: descriptor checks, the
 // per-instance view of a many-instance launch, and the loop kernels' declarations (their
-// definitions are instantiated in rr_batch_loop2/5/8.hip, one file per register-slot count, so
+// definitions are instantiated in rr_batch_loop2/5/6.hip, one file per register-slot count, so
 // that the three compile in parallel).
 #pragma once
 #include "rr_device.hpp"

@@ -550,7 +550,7 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
     }
     (void)any_slow;
     if (!ok) { X.err = kOverflow; return; }
-    // keep the set in as few slots as it fits (1; with 5 or more slots also 2; with 8, 4) so
+    // keep the set in as few slots as it fits (1; with 5 or more slots also 2; with 6 or more, 4) so
     // that trips scan only those
     if (S > 1) {
         uint32_t total = 0;
@@ -564,7 +564,7 @@ __device__ __forceinline__ void trip(Ready<S> &R, LoopCtx &X, const Inst &I, con
         }
         const bool c1 = h1 && total <= (uint32_t)kWave;
         const bool c2 = S >= 5 && h2 && total <= 2u * kWave;
-        const bool c4 = S >= 8 && h4 && total <= 4u * kWave;
+        const bool c4 = S >= 6 && h4 && total <= 4u * kWave;
         if (c1 || c2 || c4) { compact(R, M.scratch); moved = true; }
     }
     if (ldone || moved) find_leader(R, X.ls, X.ll, X.lc, X.le, X.ln, X.lk);
@@ -628,7 +628,7 @@ __device__ __forceinline__ bool loop_run(const Inst &I, const LoopMem &M, uint32
         }
         if (!h1) trip<1, S, flags>(R, X, I, M);
         else if (S >= 5 && !h2) trip<(S >= 5 ? 2 : S), S, flags>(R, X, I, M);
-        else if (S >= 8 && !h4) trip<(S >= 8 ? 4 : S), S, flags>(R, X, I, M);
+        else if (S >= 6 && !h4) trip<(S >= 6 ? 4 : S), S, flags>(R, X, I, M);
         else trip<S, S, flags>(R, X, I, M);
         if (X.err) break;
     }

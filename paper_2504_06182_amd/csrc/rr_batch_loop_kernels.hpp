@@ -1,5 +1,5 @@
 // rr_batch_loop_kernels.hpp -- definitions of the loop kernels of the batching routine (§IV,
-// Alg. 3): included by rr_batch_loop2/5/8.hip, each instantiating one register-slot count.
+// Alg. 3): included by rr_batch_loop2/5/6.hip, each instantiating one register-slot count.
 #pragma once
 #include "rr_batch_common.hpp"
 #include "rr_batch_loop.hpp"

@@ -101,7 +101,7 @@ def loop_lds_floor(side: int) -> int:
     per-group counts and merge scratch: 8 B per group of at most 2 * side, 16 B per register
     position); the library raises a smaller loop budget to this, so smaller candidates are the
     same schedule."""
-    slots = 2 if side <= 64 else (5 if side <= 128 else 8)
+    slots = 2 if side <= 64 else (5 if side <= 128 else 6)
     return 8 * min(2 * side, 1024) + 16 * 64 * slots + 16
 
 
