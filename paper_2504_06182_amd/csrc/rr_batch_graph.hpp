@@ -198,33 +198,38 @@ __device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared<
     }
 }
 
-// sort a[0..n) ascending (distinct 16-bit values), one thread
+// sort a[0..n) ascending (n <= N), one thread: a bitonic network over N registers
+template <int N>
+__device__ __forceinline__ void sort_regs(uint16_t *a, int n)
+{
+    uint32_t r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = i < n ? (uint32_t)a[i] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const uint32_t lo = r[i] < r[l] ? r[i] : r[l], hi = r[i] < r[l] ? r[l] : r[i];
+                    r[i] = up ? lo : hi;
+                    r[l] = up ? hi : lo;
+                }
+            }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        if (i < n) a[i] = (uint16_t)r[i];
+}
+
+// sort a[0..n) ascending (distinct 16-bit values), one thread: in registers up to 16 entries,
+// by insertion beyond (a 32-entry network doubles the graph kernels' registers)
 __device__ __forceinline__ void sort_list(uint16_t *a, int n)
 {
     if (n <= 1) return;
-    if (n <= 16) {
-        uint32_t r[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) r[i] = i < n ? (uint32_t)a[i] : 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 2; k <= 16; k <<= 1)
-#pragma unroll
-            for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const bool up = (i & k) == 0;
-                        const uint32_t lo = r[i] < r[l] ? r[i] : r[l], hi = r[i] < r[l] ? r[l] : r[i];
-                        r[i] = up ? lo : hi;
-                        r[l] = up ? hi : lo;
-                    }
-                }
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < n) a[i] = (uint16_t)r[i];
-        return;
-    }
+    if (n <= 16) { sort_regs<16>(a, n); return; }
     for (int k = 1; k < n; ++k) {
         const uint16_t v = a[k];
         int m = k;
@@ -370,7 +375,10 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         }
     }
     __syncthreads();
-    for (uint32_t c = tid; c < WH; c += NT) {
+    // traps in column-major order: the long lists gather in a few columns (the receivers'), and
+    //   a stride of NT in row-major order would give each thread traps of one column only
+    for (uint32_t i = tid; i < WH; i += NT) {
+        const uint32_t x = i / (uint32_t)H, c = (i - x * (uint32_t)H) * (uint32_t)W + x;
         const uint32_t lo = c ? cell[c - 1] : 0u;
         sort_list(touch + lo, (int)(cell[c] - lo));
     }
