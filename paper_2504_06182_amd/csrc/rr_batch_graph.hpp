@@ -146,6 +146,7 @@ struct GraphShared {
     uint32_t flags;
     uint32_t nr;            // row ranges of the tiled build
     uint32_t nlong;         // long horizontal legs of the current range, searched wave by wave
+    uint32_t nedge;         // one-piece build: in-group edges appended so far
     uint16_t longq[512];
 };
 
@@ -173,8 +174,9 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, GraphShared<NT / kWave
     return t;
 }
 
-// exclusive scan of a[0..n) in place, a[n] = total (a: LDS or global, visible to the workgroup)
-template <int NT>
+// exclusive scan of a[0..n) in place, a[n] = total (a: LDS or global, visible to the workgroup);
+// kIncl gives a[i] = a[0] + ... + a[i] instead (the end of entry i's range)
+template <int NT, bool kIncl = false>
 __device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared<NT / kWave> &S)
 {
     const int tid = threadIdx.x, lane = lane_id(), wid = tid >> 6;
@@ -192,7 +194,7 @@ __device__ __forceinline__ void block_scan(uint32_t *a, uint32_t n, GraphShared<
             pre += w < wid ? pw : 0u;
             tot += pw;
         }
-        if (i <= n) a[i] = carry + pre + inc - v;
+        if (i <= n) a[i] = carry + pre + inc - (kIncl ? 0u : v);
         carry += tot;
         __syncthreads();
     }
@@ -319,7 +321,7 @@ __device__ __forceinline__ bool pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc
     return true;
 }
 
-template <int NT>
+template <int NT, bool kEdges>
 __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
                                           uint32_t T);
 
@@ -335,10 +337,10 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
     uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
     uint32_t *mv32 = (uint32_t *)(I.ws + L.mv);
     uint16_t *nx = (uint16_t *)(I.ws + L.nx);
-    uint32_t *soff = (uint32_t *)(I.ws + L.soff), *sfill = (uint32_t *)(I.ws + L.sfill);
-    uint32_t *slist = (uint32_t *)(I.ws + L.slist), *pend = (uint32_t *)(I.ws + L.pend);
+    uint32_t *soff = (uint32_t *)(I.ws + L.soff);
+    uint32_t *pend = (uint32_t *)(I.ws + L.pend);
     uint16_t *preds = (uint16_t *)(I.ws + L.preds);
-    uint32_t *gbits = (uint32_t *)(I.ws + L.gbits), *gcnt = (uint32_t *)(I.ws + L.gcnt), *hcnt = (uint32_t *)(I.ws + L.hcnt);
+    uint32_t *gbits = (uint32_t *)(I.ws + L.gbits);
     const uint32_t GW = L.GW;
 
     for (uint32_t g = tid; g < G; g += NT)
@@ -347,12 +349,11 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
         mv32[b] = (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
-        sfill[b] = 0;
     }
     for (uint32_t c = tid; c <= WH; c += NT) cell[c] = 0;
     for (uint32_t b = tid; b <= K; b += NT) soff[b] = 0;
     for (uint32_t i = tid; i < G * GW; i += NT) gbits[i] = 0;
-    if (tid == 0) S.flags = 0;
+    if (tid == 0) { S.flags = 0; S.nedge = 0; }
     __syncthreads();
 
     // ---- touch lists: count, scan, scatter (post-increment: afterwards trap c's list is
@@ -384,7 +385,13 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
     }
     __syncthreads();
 
-    // ---- previous toucher of every trap of every move
+    // ---- previous toucher of every trap of every move.  The in-group edges (a -> b) go to a
+    //      packed list (a | b << 16, in the region of the per-move predecessor slots, which
+    //      holds 4 * kMaxPreds 16-bit words per move, i.e. 4 edges per move on average): each wave
+    //      reserves its edges' places with one LDS atomic and places them by ballot prefix counts.
+    uint32_t *edge = (uint32_t *)preds;
+    const uint32_t ecap = 4u * K;
+    const int lane = lane_id();
     for (uint32_t b = tid; b < K; b += NT) {
         int sx, sy, dx, dy;
         load_move(I.moves, b, sx, sy, dx, dy);
@@ -415,23 +422,41 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
             }
         }
         pend[b] = (uint32_t)np;
+        // place of this move's first edge: prefix of np over the wave's active lanes (np <= 8
+        // takes four bits), the wave's block from one LDS atomic of its first active lane
+        const uint64_t below = low_mask(lane);
+        uint32_t pre = 0, tot = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint64_t m = ballot(((uint32_t)np >> k) & 1u);
+            pre += (uint32_t)popc(m & below) << k;
+            tot += (uint32_t)popc(m) << k;
+        }
+        const int leader = __builtin_ctzll(ballot(true));
+        uint32_t base = 0;
+        if (lane == leader) base = add_wg32(&S.nedge, tot);
+        base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader) + pre;
 #pragma unroll
         for (int i = 0; i < kMaxPreds; ++i)
-            if (i < np) { preds[(size_t)b * kMaxPreds + i] = (uint16_t)ps[i]; add_wg32(&soff[ps[i]], 1u); }
+            if (i < np) {
+                if (base + (uint32_t)i < ecap) edge[base + (uint32_t)i] = ps[i] | (b << 16);
+                add_wg32(&soff[ps[i]], 1u);
+            }
         if (ovf) S.flags = 1;
     }
     __syncthreads();
-    if (S.flags) {
+    if (S.flags || S.nedge > ecap) {
         if (tid == 0) hdr[H_STATE] = ST_GENERIC;
         return;
     }
-    graph_tail<NT>(I, S, L, K, G, T);
+    graph_tail<NT, true>(I, S, L, K, G, T);
 }
 
-// Second half of the graph build, from the in-group predecessor sets (pend, preds), their
-// successor counts (soff) and the group bit matrix (gbits), all in the workspace: successor
-// lists, release codes, heads, group lists and the header.
-template <int NT>
+// Second half of the graph build, from the in-group predecessor sets (pend, and either preds as
+// per-move slots or, with kEdges, the packed edge list of S.nedge entries in the same region),
+// their successor counts (soff) and the group bit matrix (gbits), all in the workspace:
+// successor lists, release codes, heads, group lists and the header.
+template <int NT, bool kEdges>
 __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
                                           uint32_t T)
 {
@@ -445,12 +470,23 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
     const uint32_t GW = L.GW;
 
     // ---- successor lists (CSR) and release codes
-    block_scan<NT>(soff, K, S);
-    for (uint32_t b = tid; b < K; b += NT) {
-        const uint32_t np = pend[b];
-        for (uint32_t i = 0; i < np; ++i) {
-            const uint32_t a = preds[(size_t)b * kMaxPreds + i];
-            slist[soff[a] + add_wg32(&sfill[a], 1u)] = b;
+    if (kEdges) {
+        // soff[a] starts at the end of a's range and counts down to its start as the list fills
+        // (the order within a list is free: the loop inserts released moves by index)
+        block_scan<NT, true>(soff, K, S);
+        const uint32_t *edge = (const uint32_t *)preds, E = S.nedge;
+        for (uint32_t e = tid; e < E; e += NT) {
+            const uint32_t v = edge[e], a = v & 0xFFFFu;
+            slist[add_wg32(&soff[a], 0xFFFFFFFFu) - 1u] = v >> 16;
+        }
+    } else {
+        block_scan<NT>(soff, K, S);
+        for (uint32_t b = tid; b < K; b += NT) {
+            const uint32_t np = pend[b];
+            for (uint32_t i = 0; i < np; ++i) {
+                const uint32_t a = preds[(size_t)b * kMaxPreds + i];
+                slist[soff[a] + add_wg32(&sfill[a], 1u)] = b;
+            }
         }
     }
     __syncthreads();
@@ -847,7 +883,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
         for (uint32_t i = 0; i < np; ++i) add_wg32(&soff[preds[(size_t)b * kMaxPreds + i]], 1u);
     }
     __syncthreads();
-    graph_tail<NT>(I, S, L, K, G, T);
+    graph_tail<NT, false>(I, S, L, K, G, T);
     return true;
 }
 
