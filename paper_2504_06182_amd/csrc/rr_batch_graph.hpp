@@ -323,13 +323,15 @@ __device__ __forceinline__ bool pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc
 
 template <int NT, bool kEdges>
 __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
-                                          uint32_t T);
+                                          uint32_t T, uint32_t *cnt);
 
 // The graph of one instance from its validated moves; cell (W*H + 1 words), grp (K) and touch
-// (K + T) are the per-trap scratch arrays.
+// (K + T) are the per-trap scratch arrays; cnt (K + 1 words, LDS or the workspace's successor
+// offsets) takes the successor counts once the per-trap arrays are no longer needed, and may
+// overlap them.
 template <int NT>
 __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
-                                           uint32_t T, uint32_t *cell, uint16_t *grp, uint16_t *touch)
+                                           uint32_t T, uint32_t *cell, uint16_t *grp, uint16_t *touch, uint32_t *cnt)
 {
     const int tid = threadIdx.x;
     const int W = I.W, H = I.H;
@@ -337,7 +339,6 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
     uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
     uint32_t *mv32 = (uint32_t *)(I.ws + L.mv);
     uint16_t *nx = (uint16_t *)(I.ws + L.nx);
-    uint32_t *soff = (uint32_t *)(I.ws + L.soff);
     uint32_t *pend = (uint32_t *)(I.ws + L.pend);
     uint16_t *preds = (uint16_t *)(I.ws + L.preds);
     uint32_t *gbits = (uint32_t *)(I.ws + L.gbits);
@@ -351,7 +352,6 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         mv32[b] = (uint32_t)sx | ((uint32_t)sy << 8) | ((uint32_t)dx << 16) | ((uint32_t)dy << 24);
     }
     for (uint32_t c = tid; c <= WH; c += NT) cell[c] = 0;
-    for (uint32_t b = tid; b <= K; b += NT) soff[b] = 0;
     for (uint32_t i = tid; i < G * GW; i += NT) gbits[i] = 0;
     if (tid == 0) { S.flags = 0; S.nedge = 0; }
     __syncthreads();
@@ -438,10 +438,7 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader) + pre;
 #pragma unroll
         for (int i = 0; i < kMaxPreds; ++i)
-            if (i < np) {
-                if (base + (uint32_t)i < ecap) edge[base + (uint32_t)i] = ps[i] | (b << 16);
-                add_wg32(&soff[ps[i]], 1u);
-            }
+            if (i < np && base + (uint32_t)i < ecap) edge[base + (uint32_t)i] = ps[i] | (b << 16);
         if (ovf) S.flags = 1;
     }
     __syncthreads();
@@ -449,16 +446,16 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         if (tid == 0) hdr[H_STATE] = ST_GENERIC;
         return;
     }
-    graph_tail<NT, true>(I, S, L, K, G, T);
+    graph_tail<NT, true>(I, S, L, K, G, T, cnt);
 }
 
 // Second half of the graph build, from the in-group predecessor sets (pend, and either preds as
-// per-move slots or, with kEdges, the packed edge list of S.nedge entries in the same region),
-// their successor counts (soff) and the group bit matrix (gbits), all in the workspace:
-// successor lists, release codes, heads, group lists and the header.
+// per-move slots with their successor counts in soff, or, with kEdges, the packed edge list of
+// S.nedge entries in the same region, counted here into cnt) and the group bit matrix (gbits),
+// all in the workspace: successor lists, release codes, heads, group lists and the header.
 template <int NT, bool kEdges>
 __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
-                                          uint32_t T)
+                                          uint32_t T, uint32_t *cnt)
 {
     const int tid = threadIdx.x;
     uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
@@ -471,15 +468,24 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
 
     // ---- successor lists (CSR) and release codes
     if (kEdges) {
-        // soff[a] starts at the end of a's range and counts down to its start as the list fills
-        // (the order within a list is free: the loop inserts released moves by index)
-        block_scan<NT, true>(soff, K, S);
+        // successor counts from the edges, an inclusive scan, then cnt[a] counts down from the
+        // end of a's range to its start as the list fills (the order within a list is free: the
+        // loop inserts released moves by index); a copy in LDS goes to soff at the end
         const uint32_t *edge = (const uint32_t *)preds, E = S.nedge;
+        for (uint32_t b = tid; b <= K; b += NT) cnt[b] = 0;
+        __syncthreads();
+        for (uint32_t e = tid; e < E; e += NT) add_wg32(&cnt[edge[e] & 0xFFFFu], 1u);
+        __syncthreads();
+        block_scan<NT, true>(cnt, K, S);
         for (uint32_t e = tid; e < E; e += NT) {
-            const uint32_t v = edge[e], a = v & 0xFFFFu;
-            slist[add_wg32(&soff[a], 0xFFFFFFFFu) - 1u] = v >> 16;
+            const uint32_t v = edge[e];
+            slist[add_wg32(&cnt[v & 0xFFFFu], 0xFFFFFFFFu) - 1u] = v >> 16;
         }
+        __syncthreads();
+        if (cnt != soff)
+            for (uint32_t b = tid; b <= K; b += NT) soff[b] = cnt[b];
     } else {
+        cnt = soff;
         block_scan<NT>(soff, K, S);
         for (uint32_t b = tid; b < K; b += NT) {
             const uint32_t np = pend[b];
@@ -492,7 +498,7 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
     __syncthreads();
     uint32_t extra = 0;
     for (uint32_t a = tid; a < K; a += NT) {
-        const uint32_t lo = soff[a], ns = soff[a + 1] - lo;
+        const uint32_t lo = cnt[a], ns = cnt[a + 1] - lo;
         uint32_t code = kRelNone << 14;
         if (ns == 1) {
             const uint32_t n = slist[lo];
@@ -534,7 +540,7 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
     }
     if (tid == 0) {
         const uint32_t HN = hcnt[G], GE = gcnt[G];
-        hdr[H_K] = K; hdr[H_G] = G; hdr[H_T] = T; hdr[H_E] = soff[K]; hdr[H_GE] = GE; hdr[H_HN] = HN;
+        hdr[H_K] = K; hdr[H_G] = G; hdr[H_T] = T; hdr[H_E] = cnt[K]; hdr[H_GE] = GE; hdr[H_HN] = HN;
         hdr[H_BOUND] = HN + extra;
         hdr[H_STATE] = (HN > 65535u || GE > 65535u) ? ST_GENERIC : ST_FAST;
     }
@@ -883,7 +889,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
         for (uint32_t i = 0; i < np; ++i) add_wg32(&soff[preds[(size_t)b * kMaxPreds + i]], 1u);
     }
     __syncthreads();
-    graph_tail<NT, false>(I, S, L, K, G, T);
+    graph_tail<NT, false>(I, S, L, K, G, T, nullptr);
     return true;
 }
 
@@ -942,10 +948,10 @@ __device__ void graph_build(const Inst &I, GraphShared<NT / kWave> &S, uint8_t *
     if (need <= lds_bytes) {
         uint16_t *grp = (uint16_t *)(lds + 4 * ((size_t)WH + 1));
         uint16_t *touch = (uint16_t *)(lds + 4 * ((size_t)WH + 1) + 2 * (((size_t)K + 1) & ~(size_t)1));
-        graph_core<NT>(I, S, L, K, G, T, (uint32_t *)lds, grp, touch);
+        graph_core<NT>(I, S, L, K, G, T, (uint32_t *)lds, grp, touch, (uint32_t *)lds);
     } else if (!graph_tiled<NT>(I, S, L, K, G, T, lds, lds_bytes)) {
         graph_core<NT>(I, S, L, K, G, T, (uint32_t *)(I.ws + L.cell), (uint16_t *)(I.ws + L.grp),
-                   (uint16_t *)(I.ws + L.touch));
+                   (uint16_t *)(I.ws + L.touch), (uint32_t *)(I.ws + L.soff));
     }
 }
 
