@@ -323,15 +323,16 @@ __device__ __forceinline__ bool pred_add(uint32_t (&s)[kMaxPreds], uint32_t (&pc
 
 template <int NT, bool kEdges>
 __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
-                                          uint32_t T, uint32_t *cnt);
+                                          uint32_t T, uint32_t *cnt, uint32_t *gt);
 
 // The graph of one instance from its validated moves; cell (W*H + 1 words), grp (K) and touch
 // (K + T) are the per-trap scratch arrays; cnt (K + 1 words, LDS or the workspace's successor
 // offsets) takes the successor counts once the per-trap arrays are no longer needed, and may
-// overlap them.
+// overlap them; so may gt (G * GW words of LDS, or null), the transposed group bit matrix.
 template <int NT>
 __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
-                                           uint32_t T, uint32_t *cell, uint16_t *grp, uint16_t *touch, uint32_t *cnt)
+                                           uint32_t T, uint32_t *cell, uint16_t *grp, uint16_t *touch, uint32_t *cnt,
+                                           uint32_t *gt)
 {
     const int tid = threadIdx.x;
     const int W = I.W, H = I.H;
@@ -446,16 +447,18 @@ __device__ __forceinline__ void graph_core(const Inst &I, GraphShared<NT / kWave
         if (tid == 0) hdr[H_STATE] = ST_GENERIC;
         return;
     }
-    graph_tail<NT, true>(I, S, L, K, G, T, cnt);
+    graph_tail<NT, true>(I, S, L, K, G, T, cnt, gt);
 }
 
 // Second half of the graph build, from the in-group predecessor sets (pend, and either preds as
 // per-move slots with their successor counts in soff, or, with kEdges, the packed edge list of
 // S.nedge entries in the same region, counted here into cnt) and the group bit matrix (gbits),
 // all in the workspace: successor lists, release codes, heads, group lists and the header.
+// gt (G * GW words of LDS, or null) takes the group bit matrix transposed: row g then holds the
+// groups waiting on g, read as a row instead of a column of the workspace matrix.
 template <int NT, bool kEdges>
 __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave> &S, const Layout &L, uint32_t K, uint32_t G,
-                                          uint32_t T, uint32_t *cnt)
+                                          uint32_t T, uint32_t *cnt, uint32_t *gt)
 {
     const int tid = threadIdx.x;
     uint32_t *hdr = (uint32_t *)(I.ws + L.hdr);
@@ -512,6 +515,17 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
     extra = block_sum<NT>(extra, S);
 
     // ---- heads of every group, and the groups waiting on every group
+    if (gt) {          // row h of gbits has bit a set when group a precedes group h
+        for (uint32_t i = tid; i < G * GW; i += NT) gt[i] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < G * GW; i += NT) {
+            const uint32_t h = i / GW, a0 = (i - h * GW) * 32u;
+            for (uint32_t m = gbits[i]; m; m &= m - 1u)
+                __hip_atomic_fetch_or(&gt[(a0 + (uint32_t)__builtin_ctz(m)) * GW + h / 32], 1u << (h & 31),
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        __syncthreads();
+    }
     uint16_t *gpend = (uint16_t *)(I.ws + L.gpend), *gloff = (uint16_t *)(I.ws + L.gloff);
     uint16_t *hdoff = (uint16_t *)(I.ws + L.hdoff), *hd = (uint16_t *)(I.ws + L.hd), *gl = (uint16_t *)(I.ws + L.gl);
     for (uint32_t g = tid; g < G; g += NT) {
@@ -520,7 +534,10 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
         hcnt[g] = c;
         uint32_t np = 0, nw = 0;
         for (uint32_t w = 0; w < GW; ++w) np += (uint32_t)__popc(gbits[g * GW + w]);
-        for (uint32_t h = 0; h < G; ++h) nw += (gbits[h * GW + g / 32] >> (g & 31)) & 1u;
+        if (gt)
+            for (uint32_t w = 0; w < GW; ++w) nw += (uint32_t)__popc(gt[g * GW + w]);
+        else
+            for (uint32_t h = 0; h < G; ++h) nw += (gbits[h * GW + g / 32] >> (g & 31)) & 1u;
         gpend[g] = (uint16_t)np;
         gcnt[g] = nw;
     }
@@ -535,8 +552,13 @@ __device__ __forceinline__ void graph_tail(const Inst &I, GraphShared<NT / kWave
         for (uint32_t b = I.goff[g]; b < I.goff[g + 1]; ++b)
             if (pend[b] == 0u) hd[o++] = (uint16_t)b;
         o = gcnt[g];
-        for (uint32_t h = 0; h < G; ++h)
-            if ((gbits[h * GW + g / 32] >> (g & 31)) & 1u) gl[o++] = (uint16_t)h;
+        if (gt) {
+            for (uint32_t w = 0; w < GW; ++w)
+                for (uint32_t m = gt[g * GW + w]; m; m &= m - 1u) gl[o++] = (uint16_t)(w * 32u + (uint32_t)__builtin_ctz(m));
+        } else {
+            for (uint32_t h = 0; h < G; ++h)
+                if ((gbits[h * GW + g / 32] >> (g & 31)) & 1u) gl[o++] = (uint16_t)h;
+        }
     }
     if (tid == 0) {
         const uint32_t HN = hcnt[G], GE = gcnt[G];
@@ -889,7 +911,7 @@ __device__ __forceinline__ bool graph_tiled(const Inst &I, GraphShared<NT / kWav
         for (uint32_t i = 0; i < np; ++i) add_wg32(&soff[preds[(size_t)b * kMaxPreds + i]], 1u);
     }
     __syncthreads();
-    graph_tail<NT, false>(I, S, L, K, G, T, nullptr);
+    graph_tail<NT, false>(I, S, L, K, G, T, nullptr, nullptr);
     return true;
 }
 
@@ -948,10 +970,14 @@ __device__ void graph_build(const Inst &I, GraphShared<NT / kWave> &S, uint8_t *
     if (need <= lds_bytes) {
         uint16_t *grp = (uint16_t *)(lds + 4 * ((size_t)WH + 1));
         uint16_t *touch = (uint16_t *)(lds + 4 * ((size_t)WH + 1) + 2 * (((size_t)K + 1) & ~(size_t)1));
-        graph_core<NT>(I, S, L, K, G, T, (uint32_t *)lds, grp, touch, (uint32_t *)lds);
+        // after the per-trap arrays: the successor counts at the start of the LDS, then the
+        // transposed group bit matrix when it fits beside them
+        const size_t gt_at = (4 * ((size_t)K + 1) + 15) & ~(size_t)15;
+        uint32_t *gt = gt_at + 4 * (size_t)G * L.GW <= lds_bytes ? (uint32_t *)(lds + gt_at) : nullptr;
+        graph_core<NT>(I, S, L, K, G, T, (uint32_t *)lds, grp, touch, (uint32_t *)lds, gt);
     } else if (!graph_tiled<NT>(I, S, L, K, G, T, lds, lds_bytes)) {
         graph_core<NT>(I, S, L, K, G, T, (uint32_t *)(I.ws + L.cell), (uint16_t *)(I.ws + L.grp),
-                   (uint16_t *)(I.ws + L.touch), (uint32_t *)(I.ws + L.soff));
+                   (uint16_t *)(I.ws + L.touch), (uint32_t *)(I.ws + L.soff), nullptr);
     }
 }
 
